@@ -1,0 +1,185 @@
+"""FP64 CPU oracle for the free-space FFT-convolution potential solve.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports,
+links or runs anything here, and nothing here imports the product library.
+
+The arithmetic lives in ``oracle.c`` (plain C, IEEE double, OpenMP over
+output cells and pencils); this module compiles it with gcc and wraps it with
+ctypes.  Functions:
+
+* :func:`direct_sum`        -- the definition, phi[i] = G dx^3 sum_j K(i-j) rho[j]
+* :func:`direct_sum_cells`  -- the same at selected cells
+* :func:`fft_conv`          -- the same via zero padding to 2N and full complex DFTs
+* :func:`fft_conv_kernel`   -- as ``fft_conv`` with a caller-supplied padded kernel
+* :func:`kernel_pad`, :func:`green_hat`, :func:`fft`, :func:`fft3`
+
+Kernel: K(d) = -1/(dx |d|) for d != 0, K(0) = -self_coeff/dx (default 2.38).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib: Optional[ctypes.CDLL] = None
+
+SELF_COEFF = 2.38
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` next to it (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    i, d = ctypes.c_int, ctypes.c_double
+    sigs = {
+        "or_set_threads": ([i], i),
+        "or_get_threads": ([], i),
+        "or_kernel_value": ([ctypes.c_long, ctypes.c_long, ctypes.c_long, d, d], d),
+        "or_direct_sum": ([i, d, d, d, dp, dp], i),
+        "or_direct_sum_cells": ([i, d, d, d, dp, i, ip, dp], i),
+        "or_fft": ([i, dp, dp, i], i),
+        "or_fft3": ([i, dp, i], i),
+        "or_kernel_pad": ([i, d, d, dp], i),
+        "or_green_hat": ([i, d, d, dp], i),
+        "or_fft_conv_kernel": ([i, d, d, dp, dp, dp], i),
+        "or_fft_conv": ([i, d, d, d, dp, dp], i),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def _cube(rho: np.ndarray) -> np.ndarray:
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    if rho.ndim != 3 or len(set(rho.shape)) != 1:
+        raise ValueError("density must be a cubic [z][y][x] array")
+    return rho
+
+
+def set_threads(n: int) -> int:
+    return _load().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return _load().or_get_threads()
+
+
+def kernel_value(di: int, dj: int, dk: int, dx: float, self_coeff: float = SELF_COEFF) -> float:
+    return _load().or_kernel_value(int(di), int(dj), int(dk), float(dx), float(self_coeff))
+
+
+def direct_sum(rho: np.ndarray, dx: float, G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
+    rho = _cube(rho)
+    n = rho.shape[0]
+    phi = np.empty_like(rho)
+    _check(_load().or_direct_sum(n, dx, G, self_coeff, _dp(rho), _dp(phi)), "direct_sum")
+    return phi
+
+
+def direct_sum_cells(rho: np.ndarray, cells: Sequence[Sequence[int]], dx: float, G: float = 1.0,
+                     self_coeff: float = SELF_COEFF) -> np.ndarray:
+    rho = _cube(rho)
+    n = rho.shape[0]
+    c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+    out = np.empty(c.shape[0], dtype=np.float64)
+    rc = _load().or_direct_sum_cells(n, dx, G, self_coeff, _dp(rho), int(c.shape[0]),
+                                     c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out))
+    _check(rc, "direct_sum_cells")
+    return out
+
+
+def fft(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.complex128).ravel()
+    out = np.empty_like(x)
+    _check(_load().or_fft(int(x.shape[0]), _dp(x.view(np.float64)), _dp(out.view(np.float64)), sign), "fft")
+    return out
+
+
+def fft3(a: np.ndarray, sign: int = -1) -> np.ndarray:
+    a = np.array(a, dtype=np.complex128, order="C", copy=True)
+    if a.ndim != 3 or len(set(a.shape)) != 1:
+        raise ValueError("fft3 needs a cubic array")
+    _check(_load().or_fft3(int(a.shape[0]), _dp(a.view(np.float64)), sign), "fft3")
+    return a
+
+
+def kernel_pad(n: int, dx: float, self_coeff: float = SELF_COEFF) -> np.ndarray:
+    p = 2 * n
+    k = np.empty((p, p, p), dtype=np.float64)
+    _check(_load().or_kernel_pad(n, dx, self_coeff, _dp(k)), "kernel_pad")
+    return k
+
+
+def green_hat(n: int, dx: float, self_coeff: float = SELF_COEFF) -> np.ndarray:
+    p = 2 * n
+    g = np.empty((p, p, p), dtype=np.complex128)
+    _check(_load().or_green_hat(n, dx, self_coeff, _dp(g.view(np.float64))), "green_hat")
+    return g
+
+
+def fft_conv_kernel(rho: np.ndarray, kpad: np.ndarray, dx: float, G: float = 1.0) -> np.ndarray:
+    rho = _cube(rho)
+    n = rho.shape[0]
+    kpad = np.ascontiguousarray(kpad, dtype=np.float64)
+    if kpad.shape != (2 * n,) * 3:
+        raise ValueError("kpad must be (2N)^3")
+    phi = np.empty_like(rho)
+    _check(_load().or_fft_conv_kernel(n, dx, G, _dp(kpad), _dp(rho), _dp(phi)), "fft_conv_kernel")
+    return phi
+
+
+def fft_conv(rho: np.ndarray, dx: float, G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
+    rho = _cube(rho)
+    n = rho.shape[0]
+    phi = np.empty_like(rho)
+    _check(_load().or_fft_conv(n, dx, G, self_coeff, _dp(rho), _dp(phi)), "fft_conv")
+    return phi
+
+
+def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
+    """||a - ref||_2 / ||ref||_2 over all cells."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm((a - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def rel_max(a: np.ndarray, ref: np.ndarray) -> float:
+    """max|a - ref| / max|ref|."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(a - ref).max() / np.abs(ref).max())

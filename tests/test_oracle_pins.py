@@ -1,0 +1,244 @@
+"""Pins for the FP64 CPU oracle, against facts fixed outside the oracle itself.
+
+Each check ties the oracle to mathematics it cannot satisfy by construction:
+brute force, closed forms, exact special cases, invariants of the convolution
+and an independent FFT library.  A dropped term, a sign error, a wrong index
+or pad length, a missing normalisation or a transposed axis breaks at least
+one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+from paper_2409_02294_amd import inputs
+
+
+def _centred_gaussian(n, sigma, mass=1.0):
+    dx = 1.0 / n
+    c = (np.arange(n) + 0.5) * dx
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2)
+    rho = mass / ((2 * math.pi) ** 1.5 * sigma ** 3) * np.exp(-r ** 2 / (2 * sigma ** 2))
+    return rho, r, dx
+
+
+# --------------------------------------------------------------------------
+# P9 / P10: the recursive FFT against a brute-force DFT, an independent FFT
+# library (numpy's pocketfft) and Parseval's identity.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", list(range(1, 25)))
+def test_fft_matches_bruteforce_dft(oracle_lib, n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    j = np.arange(n)
+    for sign in (-1, 1):
+        w = np.exp(sign * 2j * np.pi * np.outer(j, j) / n)
+        ref = w @ x
+        got = oracle_lib.fft(x, sign)
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [64, 96, 128, 192, 384, 768, 1024])
+def test_fft_matches_numpy(oracle_lib, n):
+    rng = np.random.default_rng(100 + n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    ref = np.fft.fft(x)
+    got = oracle_lib.fft(x, -1)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-14
+    inv = oracle_lib.fft(got, +1) / n
+    assert np.linalg.norm(inv - x) / np.linalg.norm(x) <= 1e-14
+    # Parseval: sum |X|^2 = n sum |x|^2
+    assert abs(np.sum(np.abs(got) ** 2) - n * np.sum(np.abs(x) ** 2)) <= 1e-13 * n * np.sum(np.abs(x) ** 2)
+
+
+@pytest.mark.parametrize("p", [4, 6, 12, 16])
+def test_fft3_matches_numpy_axes(oracle_lib, p):
+    rng = np.random.default_rng(7 * p)
+    a = rng.standard_normal((p, p, p)) + 1j * rng.standard_normal((p, p, p))
+    # anisotropic content so that a transposed axis would show
+    a[:, :, 1] *= 3.0
+    ref = np.fft.fftn(a)
+    got = oracle_lib.fft3(a, -1)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-14
+    back = oracle_lib.fft3(got, +1) / p ** 3
+    assert np.linalg.norm(back - a) / np.linalg.norm(a) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# P1: the FFT convolution equals the direct sum (the plain definition).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,seed", [(8, 1), (12, 2), (16, 3), (24, 4)])
+def test_fft_conv_equals_direct_sum_small(oracle_lib, n, seed):
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.0, 1.0, (n, n, n))
+    dx = 1.0 / n
+    a = oracle_lib.fft_conv(rho, dx)
+    b = oracle_lib.direct_sum(rho, dx)
+    assert oracle_lib.rel_l2(a, b) <= 1e-13
+    assert oracle_lib.rel_max(a, b) <= 1e-13
+
+
+def test_fft_conv_equals_direct_sum_blobs32(oracle_lib):
+    rho = inputs.workload_density("blobs32")
+    a = oracle_lib.fft_conv(rho, 1.0 / 32)
+    b = oracle_lib.direct_sum(rho, 1.0 / 32)
+    assert oracle_lib.rel_l2(a, b) <= 1e-13
+    assert oracle_lib.rel_max(a, b) <= 1e-13
+
+
+def test_fft_conv_equals_direct_sum_sampled_64(oracle_lib):
+    rho = inputs.make_density(64, 16, 77, sigma=(0.02, 0.06), noise=1e-3)
+    phi = oracle_lib.fft_conv(rho, 1.0 / 64)
+    rng = np.random.default_rng(5)
+    cells = rng.integers(0, 64, (48, 3))
+    cells[:8] = [[0, 0, 0], [63, 63, 63], [0, 63, 0], [63, 0, 63], [31, 32, 33], [0, 0, 63], [63, 0, 0], [5, 60, 17]]
+    ref = oracle_lib.direct_sum_cells(rho, cells, 1.0 / 64)
+    got = phi[cells[:, 0], cells[:, 1], cells[:, 2]]
+    assert np.abs(got - ref).max() / np.abs(ref).max() <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# P2 / P3: exact special cases.
+# --------------------------------------------------------------------------
+
+def test_single_cell_worked_example(oracle_lib):
+    # N = 1, dx = 1, rho = 5: only the self term, phi = -2.38 * G * rho * dx^2.
+    phi = oracle_lib.fft_conv(np.full((1, 1, 1), 5.0), 1.0)
+    assert abs(phi[0, 0, 0] - (-11.9)) <= 1e-13
+    phi = oracle_lib.direct_sum(np.full((1, 1, 1), 5.0), 1.0)
+    assert abs(phi[0, 0, 0] - (-11.9)) <= 1e-13
+    # G and dx scale as G * dx^2 for a single cell
+    phi = oracle_lib.fft_conv(np.full((1, 1, 1), 5.0), 0.5, G=3.0)
+    assert abs(phi[0, 0, 0] - (-2.38 * 3.0 * 5.0 * 0.25)) <= 1e-13
+
+
+@pytest.mark.parametrize("n,c", [(16, (3, 5, 7)), (12, (0, 11, 6)), (24, (23, 0, 12))])
+def test_impulse_response_is_the_kernel(oracle_lib, n, c):
+    # A unit point mass (rho = 1/dx^3 in one cell) has phi[i] = G K(i - c).
+    dx = 1.0 / n
+    rho = np.zeros((n, n, n))
+    rho[c] = 1.0 / dx ** 3
+    phi = oracle_lib.fft_conv(rho, dx, G=2.0)
+    iz, iy, ix = np.indices((n, n, n))
+    d = np.sqrt((iz - c[0]) ** 2 + (iy - c[1]) ** 2 + (ix - c[2]) ** 2)
+    with np.errstate(divide="ignore"):
+        k = np.where(d > 0, -1.0 / (dx * d), -2.38 / dx)
+    assert np.abs(phi - 2.0 * k).max() / np.abs(k).max() <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# P4 / P5: properties of the padded kernel and its transform.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [4, 6, 16])
+def test_green_hat_real_and_even(oracle_lib, n):
+    g = oracle_lib.green_hat(n, 1.0 / n)
+    p = 2 * n
+    scale = np.abs(g).max()
+    assert np.abs(g.imag).max() / scale <= 1e-15
+    neg = (-np.arange(p)) % p
+    for ax in range(3):
+        gm = np.take(g.real, neg, axis=ax)
+        assert np.abs(gm - g.real).max() / scale <= 1e-15
+    # the (0,0,0) coefficient is the sum of the padded kernel
+    k = oracle_lib.kernel_pad(n, 1.0 / n)
+    assert abs(g[0, 0, 0].real - k.sum()) <= 1e-13 * abs(k.sum())
+
+
+def test_kernel_entry_at_half_period_is_irrelevant(oracle_lib):
+    n = 16
+    dx = 1.0 / n
+    rho = np.random.default_rng(11).uniform(0.0, 1.0, (n, n, n))
+    k = oracle_lib.kernel_pad(n, dx)
+    base = oracle_lib.fft_conv_kernel(rho, k, dx)
+    k2 = k.copy()
+    k2[n, :, :] = 12345.0
+    k2[:, n, :] = 12345.0
+    k2[:, :, n] = 12345.0
+    alt = oracle_lib.fft_conv_kernel(rho, k2, dx)
+    assert oracle_lib.rel_max(alt, base) <= 1e-12
+    # ...whereas changing an entry that is reached does change the output
+    k3 = k.copy()
+    k3[n - 1, 0, 0] = 12345.0
+    assert oracle_lib.rel_max(oracle_lib.fft_conv_kernel(rho, k3, dx), base) > 1e-3
+
+
+# --------------------------------------------------------------------------
+# P6: invariants of a linear, symmetric, translation-invariant operator.
+# --------------------------------------------------------------------------
+
+def test_linearity_reciprocity_mirror(oracle_lib):
+    n = 16
+    dx = 1.0 / n
+    r1 = inputs.make_density(n, 3, 21, sigma=(0.04, 0.08))
+    r2 = np.random.default_rng(22).uniform(0.0, 1.0, (n, n, n))
+    p1 = oracle_lib.fft_conv(r1, dx)
+    p2 = oracle_lib.fft_conv(r2, dx)
+    pl = oracle_lib.fft_conv(2.0 * r1 - 3.0 * r2, dx)
+    assert oracle_lib.rel_l2(pl, 2.0 * p1 - 3.0 * p2) <= 1e-14
+    a, b = float((r1 * p2).sum()), float((r2 * p1).sum())
+    assert abs(a - b) <= 1e-14 * abs(a)
+    for ax in range(3):
+        pm = oracle_lib.fft_conv(np.flip(r1, axis=ax).copy(), dx)
+        assert oracle_lib.rel_max(np.flip(pm, axis=ax), p1) <= 1e-14
+    # swapping two axes of the density swaps them in the potential
+    pt = oracle_lib.fft_conv(np.ascontiguousarray(np.swapaxes(r1, 0, 2)), dx)
+    assert oracle_lib.rel_max(np.swapaxes(pt, 0, 2), p1) <= 1e-14
+    # translation: a density shifted by (2,1,3) cells inside the box gives the
+    # potential shifted by the same amount wherever both are defined
+    r0 = np.zeros_like(r2)
+    r0[:-2, :-1, :-3] = r2[:-2, :-1, :-3]
+    rs = np.zeros_like(r2)
+    rs[2:, 1:, 3:] = r2[:-2, :-1, :-3]
+    p0 = oracle_lib.fft_conv(r0, dx)
+    ps = oracle_lib.fft_conv(rs, dx)
+    assert oracle_lib.rel_max(ps[2:, 1:, 3:], p0[:-2, :-1, :-3]) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# P7 / P8 / P11: closed forms of continuum potentials, with the convergence
+# rate of the cell-centred discretisation.
+# --------------------------------------------------------------------------
+
+def test_gaussian_sphere_closed_form_second_order(oracle_lib):
+    sigma = 0.1
+    errs = []
+    for n in (16, 32, 64):
+        rho, r, dx = _centred_gaussian(n, sigma)
+        phi = oracle_lib.fft_conv(rho, dx)
+        m = rho.sum() * dx ** 3
+        exact = np.where(r > 0, -m * erf(r / (math.sqrt(2) * sigma)) / np.where(r > 0, r, 1.0),
+                         -m * math.sqrt(2 / math.pi) / sigma)
+        errs.append(np.linalg.norm(phi - exact) / np.linalg.norm(exact))
+    assert errs[1] < 1.5e-3 and errs[2] < 4e-4
+    for a, b in zip(errs, errs[1:]):
+        assert 3.0 < a / b < 5.0, errs
+
+
+def test_uniform_sphere_closed_form(oracle_lib):
+    errs = []
+    for n in (32, 64):
+        dx = 1.0 / n
+        c = (np.arange(n) + 0.5) * dx
+        z, y, x = np.meshgrid(c, c, c, indexing="ij")
+        r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2)
+        r0 = 0.25
+        rho = (r <= r0).astype(np.float64)
+        m = rho.sum() * dx ** 3
+        exact = np.where(r <= r0, -m * (3 * r0 ** 2 - r ** 2) / (2 * r0 ** 3), -m / np.maximum(r, 1e-300))
+        phi = oracle_lib.fft_conv(rho, dx)
+        errs.append(np.linalg.norm(phi - exact) / np.linalg.norm(exact))
+    assert errs[0] < 5e-3 and errs[1] < 2e-3 and errs[1] < errs[0]
+
+
+def test_monopole_far_field(oracle_lib):
+    n = 32
+    rho, r, dx = _centred_gaussian(n, 0.04, mass=1.5)
+    phi = oracle_lib.fft_conv(rho, dx)
+    m = rho.sum() * dx ** 3
+    for idx in [(0, 0, 0), (0, 0, n - 1), (n - 1, n - 1, n - 1), (0, n - 1, 0)]:
+        assert abs(phi[idx] - (-m / r[idx])) <= 1e-4 * abs(m / r[idx])
