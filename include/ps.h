@@ -1,0 +1,135 @@
+/*
+ * ps.h -- free-space Poisson solver by FFT convolution on one MI355X (gfx950).
+ *
+ * The operation is the potential solve of the paper's benchmark (section 3:
+ * the convolution method for potential fields on nested grids; section 1
+ * names the FFT as the performance-critical GPU operation).  For a density
+ * rho sampled on an N^3 cell-centred grid of spacing dx it computes
+ *
+ *     phi[i] = G * dx^3 * sum_{j in [0,N)^3} K(i - j) * rho[j],
+ *     K(d) = -1 / (dx |d|) for d != 0,   K(0) = -self_coeff / dx,
+ *
+ * by zero-padding rho to P = 2N per axis, a forward real-to-complex 3D FFT,
+ * a pointwise product with the pre-transformed kernel, an inverse FFT and a
+ * crop back to [0,N)^3.  Supported N: 8, 16, 24, 32, 48, 64, 96, 128, 192,
+ * 256, 384, 512 (P = 2N must be 2^a or 3*2^a, 16 <= P <= 1024).
+ *
+ * Memory.  Every pointer passed to the library is a device pointer the
+ * caller owns (e.g. torch.Tensor.data_ptr()).  rho and phi are dense
+ * C-ordered [z][y][x] arrays (x fastest) of N^3 elements: double for PS_F64
+ * and PS_F64_PLAIN, float for PS_F32, PS_F32_SPLIT and PS_F32_PLAIN; they
+ * must be aligned to their element size and must not overlap.  The library
+ * never allocates device memory: a plan's tables, transformed kernel and
+ * intermediates live in one caller-provided workspace of
+ * ps_plan_workspace_bytes() bytes, 256-byte aligned, bound to the plan by
+ * ps_green_build() and used by every later solve with that plan.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Solves
+ * are enqueued asynchronously and do not synchronise the host; they make no
+ * allocation and no host-to-device copy, so they can be captured into a HIP
+ * graph.  A plan (its workspace) serves one solve at a time: two solves with
+ * one plan must be ordered on one stream.  Results are bitwise reproducible
+ * for a given plan.
+ *
+ * Errors.  Every call returns a ps_status and never aborts.  Arguments are
+ * checked before any HIP call; ps_last_error() gives a thread-local detail
+ * string for the last failing call on this thread.
+ */
+#ifndef PS_H_
+#define PS_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_plan_s *ps_plan;
+
+typedef enum {
+    PS_OK = 0,
+    PS_ERR_INVALID = -1,     /* bad argument: NULL, misaligned, overlapping, out of range */
+    PS_ERR_UNSUPPORTED = -2, /* size or precision not supported */
+    PS_ERR_NOT_READY = -3,   /* solve before a successful ps_green_build */
+    PS_ERR_DEVICE = -4,      /* a HIP call failed (no device, launch failure, ...) */
+    PS_ERR_CAPTURE = -5      /* called under stream capture where it cannot be */
+} ps_status;
+
+typedef enum {
+    PS_F64 = 0,       /* pruned, fused pipeline in double */
+    PS_F32 = 1,       /* pruned, fused pipeline in float; kernel and twiddles built in double, rounded once */
+    PS_F32_SPLIT = 2, /* as PS_F32, radix-16 DFTs on bf16 matrix cores with split operands, fp32 accumulation */
+    PS_F64_PLAIN = 3, /* the plain method in double: padded grid, full 3D R2C, product, full C2R, crop */
+    PS_F32_PLAIN = 4  /* the plain method in float */
+} ps_precision;
+
+typedef struct {
+    int n;                  /* cells per side */
+    int p;                  /* padded length 2n */
+    int h;                  /* half-spectrum length n + 1 */
+    int precision;          /* ps_precision */
+    double dx;              /* cell size */
+    size_t workspace_bytes; /* as ps_plan_workspace_bytes */
+    size_t ghat_bytes;      /* bytes of the stored kernel spectrum (real octant) */
+    int ready;              /* 1 after a successful ps_green_build */
+    int radices[8];         /* forward radix plan, 0-terminated */
+} ps_plan_info;
+
+/* Create a plan for an n^3 grid of spacing dx (> 0) in the given precision.
+ * Host work only (radix plan, twiddle tables in double then rounded once to
+ * the plan's type, workspace layout); no HIP call.  tune_cache may name a
+ * tuning file written by ps_autotune, or be NULL.  On success *out owns a
+ * host object to release with ps_plan_destroy. */
+ps_status ps_plan_create(ps_plan *out, int n, double dx, ps_precision prec, const char *tune_cache);
+
+/* Bytes of device workspace the plan needs (transformed kernel, tables,
+ * intermediates, and the scratch of ps_green_build). */
+ps_status ps_plan_workspace_bytes(ps_plan p, size_t *bytes);
+
+/* Plan facts; see ps_plan_info. */
+ps_status ps_plan_query(ps_plan p, ps_plan_info *info);
+
+/* Build the transformed kernel in double precision on the GPU into the
+ * caller's workspace and bind that workspace to the plan: uploads the
+ * twiddle tables, generates K_pad (self cell -self_coeff/dx), transforms it,
+ * scales by G dx^3 / P^3 and stores the real octant in the plan's type.
+ * Synchronises `stream`.  Must not be called under stream capture
+ * (PS_ERR_CAPTURE).  May be called again (new G or workspace). */
+ps_status ps_green_build(ps_plan p, void *d_workspace, double G, double self_coeff, void *stream);
+
+/* One solve: phi = potential of rho, enqueued on `stream`. */
+ps_status ps_solve(ps_plan p, const void *d_rho, void *d_phi, void *stream);
+
+/* count independent solves (plans may differ in n and precision; each plan
+ * at most once per call, each built) in one persistent launch on `stream`.
+ * The first call with a given list of plans and arrays uploads a small work
+ * list into plans[0]'s workspace and so must not be under stream capture
+ * (PS_ERR_CAPTURE); later calls with the same list are capture-safe. */
+ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d_rho, void *const *d_phi,
+                           void *stream);
+
+/* Release the host object (the workspace stays the caller's). NULL is a no-op. */
+void ps_plan_destroy(ps_plan p);
+
+/* Static description of a status code. */
+const char *ps_status_str(ps_status s);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char *ps_last_error(void);
+
+/* Test hook: run a single pass of the pruned pipeline of a built plan on
+ * caller arrays, in the layouts the pipeline uses between passes
+ * (H = n + 1, P = 2n; complex = interleaved re, im of the plan's type):
+ *   pass 0  x R2C   in rho[z][y][x] (n^3 real)      -> out T1[kx][z][y] (H n n complex)
+ *   pass 1  y fwd   in T1                           -> out T2[kx][ky][z] (H P n complex)
+ *   pass 2  z conv  in T2 -> out T2 (in may equal out), forward z FFT, product, inverse, crop
+ *   pass 3  y inv   in T2                           -> out T1
+ *   pass 4  x C2R   in T1                           -> out phi[z][y][x]
+ * Not for PLAIN precisions (PS_ERR_UNSUPPORTED). */
+ps_status ps_debug_pass(ps_plan p, int pass, const void *d_in, void *d_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PS_H_ */

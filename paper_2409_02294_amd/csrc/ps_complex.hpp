@@ -1,0 +1,173 @@
+// Complex arithmetic and small in-register DFTs for the gfx950 kernels.
+//
+// Sign convention: DIR = -1 is the forward transform, exp(-2 pi i jk / n);
+// DIR = +1 the inverse, exp(+2 pi i jk / n), neither normalised.  The
+// constants are written in double precision and rounded once to T.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ps {
+
+template <typename T> struct cx_of;
+template <> struct cx_of<float> { using type = float2; };
+template <> struct cx_of<double> { using type = double2; };
+template <typename T> using cx = typename cx_of<T>::type;
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b)
+{
+    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b)
+{
+    return V{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { return V{a.x, -a.y}; }
+template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) { return V{a.x * s, a.y * s}; }
+// a * w for w = DIR ? conj : plain, used to apply a forward-sign table entry in either direction
+template <int DIR, typename V> __device__ __forceinline__ V ctw(V a, V w)
+{
+    if constexpr (DIR < 0) return cmul(a, w);
+    else return cmulc(a, w);
+}
+// a * (DIR i)
+template <int DIR, typename V> __device__ __forceinline__ V crot(V a)
+{
+    if constexpr (DIR < 0) return V{a.y, -a.x};
+    else return V{-a.y, a.x};
+}
+
+// a * exp(DIR * 2 pi i * M / 16), M in [0, 16)
+template <int DIR, int M, typename V> __device__ __forceinline__ V w16(V a)
+{
+    using T = decltype(a.x);
+    constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+    constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+    constexpr double H = 0.70710678118654752440;   // sqrt(1/2)
+    constexpr int m = M & 15;
+    if constexpr (m == 0) return a;
+    else if constexpr (m == 4) return crot<DIR>(a);
+    else if constexpr (m == 8) return V{-a.x, -a.y};
+    else if constexpr (m == 12) return crot<-DIR>(a);
+    else if constexpr (m == 2 || m == 6 || m == 10 || m == 14) {
+        // exp(DIR i pi m/8) with m/2 odd: (+-H, +-H)
+        constexpr double cr = (m == 2 || m == 14) ? H : -H;
+        constexpr double ci0 = (m == 2 || m == 6) ? H : -H;
+        constexpr double ci = DIR < 0 ? -ci0 : ci0;
+        const T c = T(cr), s = T(ci);
+        return V{a.x * c - a.y * s, a.x * s + a.y * c};
+    } else {
+        // odd m: cos / sin of m pi / 8
+        constexpr int q = m;  // 1,3,5,7,9,11,13,15
+        constexpr double cr = (q == 1 || q == 15) ? C1 : (q == 3 || q == 13) ? S1 : (q == 5 || q == 11) ? -S1 : -C1;
+        constexpr double si0 = (q == 1 || q == 7) ? S1 : (q == 3 || q == 5) ? C1 : (q == 9 || q == 15) ? -S1 : -C1;
+        constexpr double ci = DIR < 0 ? -si0 : si0;
+        const T c = T(cr), s = T(ci);
+        return V{a.x * c - a.y * s, a.x * s + a.y * c};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// In-register DFTs, natural order in and out: v[k] <- sum_j v[j] w_R^(jk).
+// ---------------------------------------------------------------------------
+
+template <int DIR, typename V> __device__ __forceinline__ void dft2(V* v)
+{
+    V a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <int DIR, typename V> __device__ __forceinline__ void dft4v(V& a0, V& a1, V& a2, V& a3)
+{
+    V t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = crot<DIR>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+template <int DIR, typename V> __device__ __forceinline__ void dft4(V* v) { dft4v<DIR>(v[0], v[1], v[2], v[3]); }
+
+template <int DIR, typename V> __device__ __forceinline__ void dft3(V* v)
+{
+    using T = decltype(v[0].x);
+    constexpr double S3 = 0.86602540378443864676;  // sqrt(3)/2
+    V a0 = v[0], a1 = v[1], a2 = v[2];
+    V t = cadd(a1, a2);
+    V m = V{a0.x - T(0.5) * t.x, a0.y - T(0.5) * t.y};
+    V d = csub(a1, a2);
+    // s = d * (DIR i sqrt3/2)
+    const T s3 = T(S3);
+    V s = crot<DIR>(V{d.x * s3, d.y * s3});
+    v[0] = cadd(a0, t);
+    v[1] = cadd(m, s);
+    v[2] = csub(m, s);
+}
+
+template <int DIR, typename V> __device__ __forceinline__ void dft8(V* v)
+{
+    V e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    V o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4v<DIR>(e0, e1, e2, e3);
+    dft4v<DIR>(o0, o1, o2, o3);
+    o1 = w16<DIR, 2>(o1);
+    o2 = w16<DIR, 4>(o2);
+    o3 = w16<DIR, 6>(o3);
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+template <int DIR, typename V> __device__ __forceinline__ void dft16(V* v)
+{
+    V y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        V a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
+        dft4v<DIR>(a0, a1, a2, a3);
+        y[n2][0] = a0;
+        y[n2][1] = a1;
+        y[n2][2] = a2;
+        y[n2][3] = a3;
+    }
+    y[1][1] = w16<DIR, 1>(y[1][1]);
+    y[1][2] = w16<DIR, 2>(y[1][2]);
+    y[1][3] = w16<DIR, 3>(y[1][3]);
+    y[2][1] = w16<DIR, 2>(y[2][1]);
+    y[2][2] = w16<DIR, 4>(y[2][2]);
+    y[2][3] = w16<DIR, 6>(y[2][3]);
+    y[3][1] = w16<DIR, 3>(y[3][1]);
+    y[3][2] = w16<DIR, 6>(y[3][2]);
+    y[3][3] = w16<DIR, 9>(y[3][3]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        V a0 = y[0][k1], a1 = y[1][k1], a2 = y[2][k1], a3 = y[3][k1];
+        dft4v<DIR>(a0, a1, a2, a3);
+        v[k1] = a0;
+        v[k1 + 4] = a1;
+        v[k1 + 8] = a2;
+        v[k1 + 12] = a3;
+    }
+}
+
+template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
+{
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) dft2<DIR>(v);
+    else if constexpr (R == 3) dft3<DIR>(v);
+    else if constexpr (R == 4) dft4<DIR>(v);
+    else if constexpr (R == 8) dft8<DIR>(v);
+    else if constexpr (R == 16) dft16<DIR>(v);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+}  // namespace ps

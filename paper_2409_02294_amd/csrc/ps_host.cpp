@@ -1,0 +1,387 @@
+// C ABI of the solver: plan creation, transformed-kernel build, solves.
+//
+// The paper's boundary convention (section 2.2.2 and appendix A: device code
+// in its own shared library behind bind(C) entry points that pass raw
+// addresses, the caller keeping ownership and sharing by pointer rather than
+// by copy) is kept: every entry point takes plain device pointers and sizes,
+// validates them before any HIP call and reports a status code.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ps_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ps_status fail(ps_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+ps_status device_fail(hipError_t e, const char* where)
+{
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return PS_ERR_DEVICE;
+}
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_plain(ps_precision p) { return p == PS_F64_PLAIN || p == PS_F32_PLAIN; }
+bool is_f64(ps_precision p) { return p == PS_F64 || p == PS_F64_PLAIN; }
+
+// cos and sin of 2 pi a / L for integers, with the angle reduced exactly to
+// [0, pi/4] by quadrant and octant symmetry before the double libm call.
+void unit_root(long a, long L, double& c, double& s)
+{
+    a %= L;
+    if (a < 0) a += L;
+    const long q = (4 * a) / L;       // quadrant
+    const long t = 4 * a - q * L;     // angle within quadrant = (pi/2) t / L, t in [0, L)
+    const double half_pi = 1.57079632679489661923;
+    double c0, s0;
+    if (2 * t <= L) {
+        const double ang = half_pi * (double)t / (double)L;
+        c0 = std::cos(ang);
+        s0 = std::sin(ang);
+    } else {
+        const double ang = half_pi * (double)(L - t) / (double)L;
+        c0 = std::sin(ang);
+        s0 = std::cos(ang);
+    }
+    switch (q) {
+    case 0: c = c0; s = s0; break;
+    case 1: c = -s0; s = c0; break;
+    case 2: c = -c0; s = -s0; break;
+    default: c = s0; s = -c0; break;
+    }
+}
+
+// Twiddle rows of a radix plan (stages >= 1): per residue m < NS a row of R
+// entries exp(-2 pi i r m / (NS R)).
+std::vector<std::complex<double>> plan_table(const std::vector<int>& rad)
+{
+    std::vector<std::complex<double>> t;
+    long ns = rad.empty() ? 1 : rad[0];
+    for (size_t s = 1; s < rad.size(); ++s) {
+        const long r = rad[s];
+        for (long m = 0; m < ns; ++m)
+            for (long q = 0; q < r; ++q) {
+                double c, sn;
+                unit_root(q * m, ns * r, c, sn);
+                t.emplace_back(c, -sn);
+            }
+        ns *= r;
+    }
+    return t;
+}
+
+template <typename T> void append_table(std::vector<unsigned char>& blob, size_t& off,
+                                        const std::vector<std::complex<double>>& t)
+{
+    off = align_up(blob.size());
+    blob.resize(off + std::max<size_t>(1, t.size()) * 2 * sizeof(T), 0);
+    T* d = reinterpret_cast<T*>(blob.data() + off);
+    for (size_t i = 0; i < t.size(); ++i) {
+        d[2 * i] = (T)t[i].real();
+        d[2 * i + 1] = (T)t[i].imag();
+    }
+}
+
+bool supported_n(int n)
+{
+    static const int ok[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    for (int v : ok)
+        if (v == n) return true;
+    return false;
+}
+
+bool capturing(hipStream_t s, bool& cap, hipError_t& err)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    err = hipStreamIsCapturing(s, &st);
+    cap = st != hipStreamCaptureStatusNone;
+    return err == hipSuccess;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+struct ps_plan_s {
+    int n = 0, P = 0, H = 0;
+    double dx = 0.0;
+    ps_precision prec = PS_F64;
+    size_t real_bytes = 0;
+    std::vector<int> radices;
+    // workspace layout (byte offsets)
+    std::vector<unsigned char> tables;
+    size_t off_tab = 0, tab_bytes = 0;
+    size_t tw_f = 0, tw_i = 0, tw_f64 = 0;  // offsets inside the table blob
+    size_t off_ghat = 0, ghat_bytes = 0;
+    size_t off_t1 = 0, off_t2 = 0;          // pruned intermediates
+    size_t off_pad = 0, off_spec = 0;       // plain intermediates
+    size_t off_gscr = 0;                    // kernel-build scratch (aliases intermediates)
+    size_t ws_bytes = 0;
+    // bound state
+    unsigned char* ws = nullptr;
+    bool ready = false;
+    double G = 1.0, self_coeff = 2.38;
+};
+
+namespace {
+
+ps_status check_plan(ps_plan p)
+{
+    if (!p) return fail(PS_ERR_INVALID, "plan is NULL");
+    return PS_OK;
+}
+
+ps::PrunedBufs pruned_bufs(ps_plan p, const void* rho, void* phi, hipStream_t s)
+{
+    ps::PrunedBufs b;
+    b.rho = rho;
+    b.phi = phi;
+    b.t1 = p->ws + p->off_t1;
+    b.t2 = p->ws + p->off_t2;
+    b.ghat = p->ws + p->off_ghat;
+    b.twf = p->ws + p->off_tab + p->tw_f;
+    b.twi = p->ws + p->off_tab + p->tw_i;
+    b.stream = s;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ps_status_str(ps_status s)
+{
+    switch (s) {
+    case PS_OK: return "ok";
+    case PS_ERR_INVALID: return "invalid argument";
+    case PS_ERR_UNSUPPORTED: return "unsupported size or precision";
+    case PS_ERR_NOT_READY: return "plan has no built transformed kernel";
+    case PS_ERR_DEVICE: return "HIP device error";
+    case PS_ERR_CAPTURE: return "not allowed under stream capture";
+    }
+    return "unknown status";
+}
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, const char* tune_cache)
+{
+    (void)tune_cache;
+    if (!out) return fail(PS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(PS_ERR_INVALID, "dx must be positive and finite");
+    if ((int)prec < (int)PS_F64 || (int)prec > (int)PS_F32_PLAIN)
+        return fail(PS_ERR_INVALID, "unknown precision " + std::to_string((int)prec));
+    if (n <= 0) return fail(PS_ERR_INVALID, "n must be positive");
+    if (!supported_n(n))
+        return fail(PS_ERR_UNSUPPORTED, "n = " + std::to_string(n) +
+                                            " unsupported (2n must be 2^a or 3*2^a with 16 <= 2n <= 1024)");
+    if (prec == PS_F32_SPLIT || is_plain(prec))
+        return fail(PS_ERR_UNSUPPORTED, "precision " + std::to_string((int)prec) + " is not built into this library");
+    ps_plan p = new (std::nothrow) ps_plan_s();
+    if (!p) return fail(PS_ERR_INVALID, "out of host memory");
+    p->n = n;
+    p->P = 2 * n;
+    p->H = n + 1;
+    p->dx = dx;
+    p->prec = prec;
+    p->real_bytes = is_f64(prec) ? 8 : 4;
+    if (!ps::host_radices(p->P, p->radices)) {
+        delete p;
+        return fail(PS_ERR_UNSUPPORTED, "no radix plan");
+    }
+    const std::vector<int> inv(p->radices.rbegin(), p->radices.rend());
+    const auto tf = plan_table(p->radices), ti = plan_table(inv);
+    if (is_f64(prec)) {
+        append_table<double>(p->tables, p->tw_f, tf);
+        append_table<double>(p->tables, p->tw_i, ti);
+        p->tw_f64 = p->tw_f;
+    } else {
+        append_table<float>(p->tables, p->tw_f, tf);
+        append_table<float>(p->tables, p->tw_i, ti);
+        append_table<double>(p->tables, p->tw_f64, tf);
+    }
+    const size_t N = n, P = p->P, H = p->H, r = p->real_bytes, c = 2 * r;
+    size_t off = 0;
+    p->off_tab = off;
+    p->tab_bytes = align_up(p->tables.size());
+    off += p->tab_bytes;
+    p->off_ghat = off;
+    p->ghat_bytes = H * H * H * r;
+    off += align_up(p->ghat_bytes);
+    const size_t gscr = H * H * H * 8;
+    if (is_plain(prec)) {
+        p->off_pad = off;
+        off += align_up(P * P * P * r);
+        p->off_spec = off;
+        const size_t spec = P * P * H * c;
+        off += align_up(std::max(spec, gscr));
+        p->off_gscr = p->off_spec;
+    } else {
+        p->off_t1 = off;
+        const size_t t1 = H * N * N * c, t2 = H * P * N * c;
+        off += align_up(t1);
+        p->off_t2 = off;
+        off += align_up(t2);
+        p->off_gscr = p->off_t1;
+        if (p->off_gscr + gscr > off) off = align_up(p->off_gscr + gscr);
+    }
+    p->ws_bytes = off;
+    *out = p;
+    return PS_OK;
+}
+
+ps_status ps_plan_workspace_bytes(ps_plan p, size_t* bytes)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    *bytes = p->ws_bytes;
+    return PS_OK;
+}
+
+ps_status ps_plan_query(ps_plan p, ps_plan_info* info)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (!info) return fail(PS_ERR_INVALID, "info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->n = p->n;
+    info->p = p->P;
+    info->h = p->H;
+    info->precision = (int)p->prec;
+    info->dx = p->dx;
+    info->workspace_bytes = p->ws_bytes;
+    info->ghat_bytes = p->ghat_bytes;
+    info->ready = p->ready ? 1 : 0;
+    for (size_t i = 0; i < p->radices.size() && i < 7; ++i) info->radices[i] = p->radices[i];
+    return PS_OK;
+}
+
+void ps_plan_destroy(ps_plan p) { delete p; }
+
+ps_status ps_green_build(ps_plan p, void* d_workspace, double G, double self_coeff, void* stream)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (!d_workspace) return fail(PS_ERR_INVALID, "workspace is NULL");
+    if ((uintptr_t)d_workspace % ALIGN) return fail(PS_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (!std::isfinite(G) || !std::isfinite(self_coeff)) return fail(PS_ERR_INVALID, "G and self_coeff must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    bool cap = false;
+    hipError_t e;
+    if (!capturing(st, cap, e)) return device_fail(e, "hipStreamIsCapturing");
+    if (cap) return fail(PS_ERR_CAPTURE, "ps_green_build cannot run under stream capture");
+    p->ready = false;
+    unsigned char* ws = static_cast<unsigned char*>(d_workspace);
+    e = hipMemcpyAsync(ws + p->off_tab, p->tables.data(), p->tables.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return device_fail(e, "table upload");
+    ps::GreenBufs gb;
+    gb.g1 = reinterpret_cast<double*>(ws + p->off_gscr);
+    gb.ghat = ws + p->off_ghat;
+    gb.twf64 = ws + p->off_tab + p->tw_f64;
+    gb.dx = p->dx;
+    gb.self_coeff = self_coeff;
+    const double P3 = (double)p->P * p->P * p->P;
+    gb.scale = G * p->dx * p->dx * p->dx / P3;
+    gb.out_f32 = !is_f64(p->prec);
+    gb.plain_layout = is_plain(p->prec);
+    gb.stream = st;
+    e = ps::green_run(p->P, gb);
+    if (e != hipSuccess) return device_fail(e, "kernel build launch");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "kernel build");
+    p->ws = ws;
+    p->G = G;
+    p->self_coeff = self_coeff;
+    p->ready = true;
+    return PS_OK;
+}
+
+ps_status ps_solve(ps_plan p, const void* d_rho, void* d_phi, void* stream)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (!d_rho || !d_phi) return fail(PS_ERR_INVALID, "rho and phi must be non-NULL");
+    if ((uintptr_t)d_rho % p->real_bytes || (uintptr_t)d_phi % p->real_bytes)
+        return fail(PS_ERR_INVALID, "rho and phi must be aligned to their element size");
+    const size_t bytes = (size_t)p->n * p->n * p->n * p->real_bytes;
+    if (overlap(d_rho, bytes, d_phi, bytes)) return fail(PS_ERR_INVALID, "rho and phi overlap");
+    if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (is_plain(p->prec)) {
+        ps::PlainBufs b;
+        b.rho = d_rho;
+        b.phi = d_phi;
+        b.pad = p->ws + p->off_pad;
+        b.spec = p->ws + p->off_spec;
+        b.ghat = p->ws + p->off_ghat;
+        b.twf = p->ws + p->off_tab + p->tw_f;
+        b.twi = p->ws + p->off_tab + p->tw_i;
+        b.stream = st;
+        e = is_f64(p->prec) ? ps::plain_run_f64(p->P, b) : ps::plain_run_f32(p->P, b);
+    } else {
+        const ps::PrunedBufs b = pruned_bufs(p, d_rho, d_phi, st);
+        e = is_f64(p->prec) ? ps::pruned_run_f64(p->P, 0, 5, b) : ps::pruned_run_f32(p->P, 0, 5, b);
+    }
+    if (e != hipSuccess) return device_fail(e, "solve launch");
+    return PS_OK;
+}
+
+ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void* stream)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (is_plain(p->prec)) return fail(PS_ERR_UNSUPPORTED, "debug passes exist for the pruned pipeline only");
+    if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..4");
+    if (!d_in || !d_out) return fail(PS_ERR_INVALID, "in and out must be non-NULL");
+    if (pass != 2 && d_in == d_out) return fail(PS_ERR_INVALID, "only pass 2 may run in place");
+    if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
+    hipStream_t st = (hipStream_t)stream;
+    ps::PrunedBufs b = pruned_bufs(p, nullptr, nullptr, st);
+    void* in = const_cast<void*>(d_in);
+    switch (pass) {
+    case 0: b.rho = d_in; b.t1 = d_out; break;
+    case 1: b.t1 = in; b.t2 = d_out; break;
+    case 2: {
+        const size_t bytes = (size_t)p->H * p->P * p->n * 2 * p->real_bytes;
+        if (d_in != d_out) {
+            hipError_t e = hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return device_fail(e, "copy");
+        }
+        b.t2 = d_out;
+        break;
+    }
+    case 3: b.t2 = in; b.t1 = d_out; break;
+    case 4: b.t1 = in; b.phi = d_out; break;
+    }
+    hipError_t e = is_f64(p->prec) ? ps::pruned_run_f64(p->P, pass, pass + 1, b)
+                                   : ps::pruned_run_f32(p->P, pass, pass + 1, b);
+    if (e != hipSuccess) return device_fail(e, "pass launch");
+    return PS_OK;
+}
+
+ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d_rho, void* const* d_phi,
+                           void* stream)
+{
+    (void)stream;
+    if (!plans || !d_rho || !d_phi) return fail(PS_ERR_INVALID, "plans, rho and phi lists must be non-NULL");
+    if (count <= 0) return fail(PS_ERR_INVALID, "count must be positive");
+    return fail(PS_ERR_UNSUPPORTED, "batched solves are not built into this library");
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Host-side internals shared by the ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ps.h"
+
+namespace ps {
+
+// Device buffers of one solve of the pruned pipeline.  Complex arrays are
+// interleaved (re, im) of the plan's real type.
+struct PrunedBufs {
+    const void* rho;   // N^3 real
+    void* phi;         // N^3 real
+    void* t1;          // [H][N][N] complex
+    void* t2;          // [H][P][N] complex
+    const void* ghat;  // [H][H][H] real octant, scaled
+    const void* twf;   // forward-plan twiddles
+    const void* twi;   // inverse-plan twiddles
+    hipStream_t stream;
+};
+
+// Runs passes [lo, hi) of the pruned pipeline (0 x_r2c, 1 y_fwd, 2 z_conv,
+// 3 y_inv, 4 x_c2r).  Returns hipErrorInvalidValue for an unsupported P.
+hipError_t pruned_run_f32(int P, int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_f64(int P, int lo, int hi, const PrunedBufs& b);
+
+// Transformed-kernel build (double precision throughout).
+struct GreenBufs {
+    double* g1;          // [H][H][H] scratch
+    void* ghat;          // output, float or double
+    const void* twf64;   // forward-plan twiddles in double
+    double dx, self_coeff, scale;
+    bool out_f32;
+    bool plain_layout;   // [kz][ky][kx] instead of [kx][ky][kz]
+    hipStream_t stream;
+};
+hipError_t green_run(int P, const GreenBufs& b);
+
+// The plain method: materialised padded grid and full half spectrum.
+struct PlainBufs {
+    const void* rho;   // N^3 real
+    void* phi;         // N^3 real
+    void* pad;         // P^3 real (padded density, later the padded potential)
+    void* spec;        // [P][P][H] complex (kx fastest)
+    const void* ghat;  // [H][H][H] real octant in [kz][ky][kx] layout
+    const void* twf;
+    const void* twi;
+    hipStream_t stream;
+};
+hipError_t plain_run_f32(int P, const PlainBufs& b);
+hipError_t plain_run_f64(int P, const PlainBufs& b);
+
+// Radix plans (forward; the inverse is the reverse) for a supported P.
+bool host_radices(int P, std::vector<int>& fwd);
+
+}  // namespace ps

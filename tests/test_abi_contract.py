@@ -1,0 +1,137 @@
+"""The C ABI's contract, exercised without a GPU.
+
+Argument validation happens before any HIP call, so every error path below
+runs on a host without a device.  The library must load and export every
+function ``include/ps.h`` declares.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT, gpu_available
+from paper_2409_02294_amd import solver as S
+
+HEADER = os.path.join(ROOT, "include", "ps.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ps_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.load()
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(S.EXPORTS)
+
+
+def test_status_strings():
+    for code in (S.PS_OK, S.PS_ERR_INVALID, S.PS_ERR_UNSUPPORTED, S.PS_ERR_NOT_READY, S.PS_ERR_DEVICE,
+                 S.PS_ERR_CAPTURE):
+        assert S.ps_status_str(code)
+    assert S.ps_status_str(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("n,dx,prec,status", [
+    (0, 0.1, S.PS_F64, S.PS_ERR_INVALID),
+    (-4, 0.1, S.PS_F64, S.PS_ERR_INVALID),
+    (32, 0.0, S.PS_F64, S.PS_ERR_INVALID),
+    (32, -1.0, S.PS_F32, S.PS_ERR_INVALID),
+    (32, float("nan"), S.PS_F32, S.PS_ERR_INVALID),
+    (32, float("inf"), S.PS_F32, S.PS_ERR_INVALID),
+    (32, 0.1, 7, S.PS_ERR_INVALID),
+    (32, 0.1, -1, S.PS_ERR_INVALID),
+    (40, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),   # 80 = 2^4 * 5
+    (1024, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),  # beyond the largest compiled length
+    (7, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),
+])
+def test_plan_create_rejects(n, dx, prec, status):
+    with pytest.raises(S.PSError) as e:
+        S.ps_plan_create(n, dx, prec)
+    assert e.value.status == status
+    assert S.ps_last_error()
+
+
+def test_plan_create_null_out():
+    lib = S.load()
+    assert lib.ps_plan_create(None, 32, 0.1, S.PS_F64, None) == S.PS_ERR_INVALID
+
+
+@pytest.mark.parametrize("n", S.SUPPORTED_N)
+@pytest.mark.parametrize("prec", [S.PS_F64, S.PS_F32])
+def test_plan_layout_and_query(n, prec):
+    p = S.ps_plan_create(n, 1.0 / n, prec)
+    try:
+        info = S.ps_plan_query(p)
+        assert info["n"] == n and info["p"] == 2 * n and info["h"] == n + 1
+        assert not info["ready"]
+        prod = 1
+        for r in info["radices"]:
+            assert r in (2, 3, 4, 8, 16)
+            prod *= r
+        assert prod == 2 * n
+        assert info["radices"][0] == 16
+        rb = 8 if prec == S.PS_F64 else 4
+        h = n + 1
+        assert info["ghat_bytes"] == h ** 3 * rb
+        ws = S.ps_plan_workspace_bytes(p)
+        # Ghat + T1 (H N N complex) + T2 (H 2N N complex) at least
+        assert ws >= h ** 3 * rb + 3 * h * n * n * 2 * rb
+        assert ws % 256 == 0
+    finally:
+        S.ps_plan_destroy(p)
+
+
+def test_calls_on_unbuilt_plan():
+    lib = S.load()
+    p = S.ps_plan_create(32, 1.0 / 32, S.PS_F64)
+    try:
+        # NULL / misaligned / overlapping pointers are rejected first
+        assert lib.ps_solve(p, None, 0x1000, None) == S.PS_ERR_INVALID
+        assert lib.ps_solve(p, 0x1000, None, None) == S.PS_ERR_INVALID
+        assert lib.ps_solve(p, 0x1004, 0x100000, None) == S.PS_ERR_INVALID
+        assert lib.ps_solve(p, 0x100000, 0x100000 + 8, None) == S.PS_ERR_INVALID
+        # well-formed arguments on a plan without a built kernel
+        assert lib.ps_solve(p, 0x100000, 0x10000000, None) == S.PS_ERR_NOT_READY
+        assert lib.ps_debug_pass(p, 0, 0x100000, 0x10000000, None) == S.PS_ERR_NOT_READY
+        assert lib.ps_debug_pass(p, 5, 0x100000, 0x10000000, None) == S.PS_ERR_INVALID
+        assert lib.ps_debug_pass(p, 1, 0x100000, 0x100000, None) == S.PS_ERR_INVALID
+        assert lib.ps_green_build(p, None, 1.0, 2.38, None) == S.PS_ERR_INVALID
+        assert lib.ps_green_build(p, 0x100010, 1.0, 2.38, None) == S.PS_ERR_INVALID
+        assert lib.ps_green_build(p, 0x100000, float("nan"), 2.38, None) == S.PS_ERR_INVALID
+    finally:
+        S.ps_plan_destroy(p)
+
+
+def test_null_plan_and_batch_arguments():
+    lib = S.load()
+    assert lib.ps_solve(None, 0x100000, 0x10000000, None) == S.PS_ERR_INVALID
+    assert lib.ps_plan_workspace_bytes(None, None) == S.PS_ERR_INVALID
+    assert lib.ps_plan_query(None, None) == S.PS_ERR_INVALID
+    lib.ps_plan_destroy(None)
+    arr = ctypes.c_void_p * 1
+    assert lib.ps_solve_batched(None, 1, arr(0x1000), arr(0x2000), None) == S.PS_ERR_INVALID
+    p = S.ps_plan_create(16, 1.0 / 16, S.PS_F32)
+    try:
+        assert lib.ps_solve_batched(arr(p), 0, arr(0x100000), arr(0x10000000), None) == S.PS_ERR_INVALID
+        assert lib.ps_solve_batched(arr(p), -3, arr(0x100000), arr(0x10000000), None) == S.PS_ERR_INVALID
+    finally:
+        S.ps_plan_destroy(p)
+
+
+@pytest.mark.skipif(gpu_available(), reason="needs a host without a GPU")
+def test_device_errors_are_reported_not_raised():
+    lib = S.load()
+    p = S.ps_plan_create(16, 1.0 / 16, S.PS_F64)
+    try:
+        rc = lib.ps_green_build(p, 0x100000, 1.0, 2.38, None)
+        assert rc == S.PS_ERR_DEVICE
+        assert S.ps_last_error()
+    finally:
+        S.ps_plan_destroy(p)

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances: rel-L2 <= 1e-12 for double-precision plans and <= 1e-6 for
+single-precision plans, with the max-norm error reported beside it.  A
+single-precision plan reads the density rounded to float32, so it is judged
+against the oracle run on that same rounded density (input rounding is not
+solver error).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import gpu_available
+from paper_2409_02294_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_2409_02294_amd import solver as S
+
+
+TOL = {"f64": 1e-12, "f32": 1e-6}
+
+
+def _dtype(prec):
+    return torch.float64 if prec.startswith("f64") else torch.float32
+
+
+def gpu_solve(rho_np, prec, dx=None, G=1.0, self_coeff=2.38):
+    n = rho_np.shape[0]
+    s = S.Solver(n, dx if dx is not None else 1.0 / n, prec, G=G, self_coeff=self_coeff)
+    rho = torch.from_numpy(np.ascontiguousarray(rho_np)).to(device="cuda", dtype=_dtype(prec))
+    phi = s(rho)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy().astype(np.float64), rho.cpu().numpy().astype(np.float64), s
+
+
+def _report(tag, got, ref):
+    l2, mx = oracle.rel_l2(got, ref), oracle.rel_max(got, ref)
+    print(f"{tag}: relL2={l2:.3e} relMax={mx:.3e}", flush=True)
+    return l2, mx
+
+
+# ---------------------------------------------------------------------------
+# Single passes of the pruned pipeline against numpy's FFT, one axis at a time
+# ---------------------------------------------------------------------------
+
+def _ghat_octant(n, dx, G=1.0):
+    p = 2 * n
+    g = oracle.green_hat(n, dx).real * (G * dx ** 3 / p ** 3)   # [kz][ky][kx]
+    h = n + 1
+    return np.ascontiguousarray(np.transpose(g[:h, :h, :h], (2, 1, 0)))  # [kx][ky][kz]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [8, 24, 32, 48])
+def test_passes_match_numpy(prec, n):
+    rng = np.random.default_rng(n)
+    p, h = 2 * n, n + 1
+    dt = _dtype(prec)
+    cdt = torch.complex128 if dt == torch.float64 else torch.complex64
+    tol = 1e-13 if prec == "f64" else 2e-6
+    plan = S.Solver(n, 1.0 / n, prec)
+    st = torch.cuda.current_stream().cuda_stream
+
+    def run(pass_id, x_np, out_shape, out_complex):
+        x = torch.from_numpy(x_np).to("cuda")
+        x = x.to(cdt if np.iscomplexobj(x_np) else dt).contiguous()
+        out = torch.empty(out_shape, dtype=cdt if out_complex else dt, device="cuda")
+        S.ps_debug_pass(plan.plan, pass_id, x.data_ptr(), out.data_ptr(), st)
+        torch.cuda.synchronize()
+        return x.cpu().numpy().astype(np.complex128 if np.iscomplexobj(x_np) else np.float64), out.cpu().numpy()
+
+    def check(tag, got, ref):
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"pass {tag} n={n} {prec}: rel max err {err:.2e}", flush=True)
+        assert err <= tol
+
+    # pass 0: real FFT along x with zero padding to P
+    rho = rng.uniform(-1, 1, (n, n, n))
+    rho_in, t1 = run(0, rho, (h, n, n), True)
+    ref = np.transpose(np.fft.rfft(rho_in, n=p, axis=2), (2, 0, 1))
+    check("x_r2c", t1, ref)
+    # pass 1: FFT along y with zero padding
+    a = rng.standard_normal((h, n, n)) + 1j * rng.standard_normal((h, n, n))
+    a_in, t2 = run(1, a, (h, p, n), True)
+    ref = np.transpose(np.fft.fft(a_in, n=p, axis=2), (0, 2, 1))
+    check("y_fwd", t2, ref)
+    # pass 2: FFT along z (zero padded), product with the kernel octant, inverse, crop
+    b = rng.standard_normal((h, p, n)) + 1j * rng.standard_normal((h, p, n))
+    b_in, t3 = run(2, b, (h, p, n), True)
+    go = _ghat_octant(n, 1.0 / n)
+    fold = np.minimum(np.arange(p), p - np.arange(p))
+    gfull = go[:, fold, :][:, :, fold]                      # [kx][ky][kz]
+    ref = np.fft.ifft(np.fft.fft(b_in, n=p, axis=2) * gfull, axis=2)[:, :, :n] * p
+    check("z_conv", t3, ref)
+    # pass 3: inverse FFT along y, crop
+    c = rng.standard_normal((h, p, n)) + 1j * rng.standard_normal((h, p, n))
+    c_in, t4 = run(3, c, (h, n, n), True)
+    ref = np.transpose(np.fft.ifft(c_in, axis=1)[:, :n, :] * p, (0, 2, 1))
+    check("y_inv", t4, ref)
+    # pass 4: inverse real FFT along x, crop
+    d = rng.standard_normal((h, n, n)) + 1j * rng.standard_normal((h, n, n))
+    d_in, out = run(4, d, (n, n, n), False)
+    spec = np.transpose(d_in, (1, 2, 0))                    # [z][y][kx]
+    ref = np.fft.irfft(spec, n=p, axis=2)[:, :, :n] * p
+    check("x_c2r", out, ref)
+
+
+# ---------------------------------------------------------------------------
+# Whole solves against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [8, 16, 24, 32, 48, 64, 96])
+def test_solve_matches_oracle_fft_conv(prec, n):
+    rho = inputs.make_density(n, 6, 300 + n, sigma=(0.03, 0.1), noise=1e-3)
+    got, rho_used, _ = gpu_solve(rho, prec)
+    ref = oracle.fft_conv(rho_used, 1.0 / n)
+    l2, mx = _report(f"n={n} {prec}", got, ref)
+    assert l2 <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_blobs32_matches_direct_sum(prec):
+    rho = inputs.workload_density("blobs32")
+    got, rho_used, _ = gpu_solve(rho, prec)
+    ref = oracle.direct_sum(rho_used, 1.0 / 32)
+    l2, mx = _report(f"blobs32 {prec} vs direct sum", got, ref)
+    assert l2 <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_nonunit_G_dx_self(prec):
+    n = 24
+    rho = inputs.make_density(n, 4, 77, sigma=(0.04, 0.1))
+    dx, G, sc = 0.37, 6.674e-3, 2.3800774
+    got, rho_used, _ = gpu_solve(rho, prec, dx=dx, G=G, self_coeff=sc)
+    ref = oracle.fft_conv(rho_used, dx, G=G, self_coeff=sc)
+    l2, _ = _report(f"n={n} {prec} G/dx/self", got, ref)
+    assert l2 <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_impulse_response_on_gpu(prec):
+    # a unit point mass gives phi[i] = G K(i - c): no oracle involved
+    n = 32
+    dx = 1.0 / n
+    c = (5, 17, 30)
+    rho = np.zeros((n, n, n))
+    rho[c] = 1.0 / dx ** 3
+    got, _, _ = gpu_solve(rho, prec)
+    iz, iy, ix = np.indices((n, n, n))
+    d = np.sqrt((iz - c[0]) ** 2 + (iy - c[1]) ** 2 + (ix - c[2]) ** 2)
+    with np.errstate(divide="ignore"):
+        k = np.where(d > 0, -1.0 / (dx * d), -2.38 / dx)
+    l2, mx = _report(f"impulse {prec}", got, k)
+    assert mx <= (1e-12 if prec == "f64" else 2e-6)
+
+
+def test_linearity_and_determinism_on_gpu():
+    n = 48
+    r1 = inputs.make_density(n, 5, 1, sigma=(0.03, 0.08))
+    r2 = np.random.default_rng(2).uniform(0, 1, (n, n, n))
+    s = S.Solver(n, 1.0 / n, "f64")
+    t1 = torch.from_numpy(r1).cuda()
+    t2 = torch.from_numpy(r2).cuda()
+    p1 = s(t1)
+    p1b = s(t1)
+    p2 = s(t2)
+    pl = s((2.0 * t1 - 3.0 * t2).contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p1b)
+    assert oracle.rel_l2(pl.cpu().numpy(), (2 * p1 - 3 * p2).cpu().numpy()) <= 1e-13
+    # reciprocity <rho1, phi[rho2]> = <rho2, phi[rho1]>
+    a = float((t1 * p2).sum())
+    b = float((t2 * p1).sum())
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+# ---------------------------------------------------------------------------
+# Larger configurations: full oracle where it fits, sampled direct sums beyond
+# ---------------------------------------------------------------------------
+
+def _sample_cells(n, k, seed):
+    rng = np.random.default_rng(seed)
+    cells = rng.integers(0, n, (k, 3))
+    corners = [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0], [n - 1, 0, n - 1], [n // 2, n // 2, n // 2]]
+    cells[:len(corners)] = corners
+    return cells
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_n128_full_oracle(prec):
+    n = 128
+    rho = inputs.make_density(n, 32, 1128, sigma=(0.01, 0.05), noise=1e-3)
+    got, rho_used, _ = gpu_solve(rho, prec)
+    ref = oracle.fft_conv(rho_used, 1.0 / n)
+    l2, mx = _report(f"n=128 {prec}", got, ref)
+    assert l2 <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_blobs256_sampled_direct_sum(prec):
+    rho = inputs.workload_density("blobs256")
+    got, rho_used, _ = gpu_solve(rho, prec)
+    cells = _sample_cells(256, 96, 7)
+    ref = oracle.direct_sum_cells(rho_used, cells, 1.0 / 256)
+    g = got[cells[:, 0], cells[:, 1], cells[:, 2]]
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print(f"blobs256 {prec}: sampled rel max err {err:.3e}", flush=True)
+    assert err <= TOL[prec]
