@@ -1,0 +1,304 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the FFT-convolution Poisson solve on one MI355X.
+
+Workload: one 512^3 solve (padded to 1024^3), density = 256 seeded Gaussian
+blobs (widths 0.01-0.05) plus uniform noise at 1e-3 of the peak, already
+resident in HBM.  A step is one complete solve (x R2C, y forward, fused z
+forward / kernel product / inverse, y inverse, x C2R + crop).
+
+Prints one JSON line: solves/s of the headline precision, the FP64 and plain
+FP64 paths beside it, per-pass times from HIP events on the solve's stream,
+the roofline record of the dominant kernel, sampled accuracy against direct
+summation, and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision P]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PASS_NAMES = ["x_r2c", "y_fwd", "z_conv", "y_inv", "x_c2r"]
+METRIC = "Poisson solves/s + HBM GB/s at 512^3, FP32-split vs FP64, at rel-L2 <=1e-6"
+
+
+def pass_bytes(n: int, rb: int):
+    """Algorithmic HBM bytes per launch of each pass (read + write, once each)."""
+    p, h, cb = 2 * n, n + 1, 2 * rb
+    t1 = h * n * n * cb
+    t2 = h * p * n * cb
+    return {
+        "x_r2c": n ** 3 * rb + t1,
+        "y_fwd": t1 + t2,
+        "z_conv": 2 * t2 + h ** 3 * rb,
+        "y_inv": t2 + t1,
+        "x_c2r": t1 + n ** 3 * rb,
+    }
+
+
+def model_bytes(n: int, rb: int):
+    """Per-solve byte models: B2 (two round trips of the N x P x H intermediate)
+    and B3 (one round trip per axis, what the five passes move)."""
+    p, h, cb = 2 * n, n + 1, 2 * rb
+    b0 = 2 * n ** 3 * rb + h ** 3 * rb
+    return {"B0": b0, "B2": 8 * n * n * h * cb + b0, "B3": 12 * n * n * h * cb + b0}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2409_02294_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, n: int, prec: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        rec = d["kernels"][f"{kernel}/n{n}/{prec}"]
+        if rec.get("source_hash") != source_hash():
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def time_solves(torch, s, rho, phi, steps, warmup):
+    for _ in range(warmup):
+        s(rho, phi)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        s(rho, phi)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def time_passes(torch, S, s, rho, phi, steps):
+    """Mean duration of each pass, from HIP events recorded between the passes
+    on the stream they are launched on."""
+    info = s.info()
+    ws = s.workspace.data_ptr()
+    t1, t2 = ws + info["t1_offset"], ws + info["t2_offset"]
+    io = [(rho.data_ptr(), t1), (t1, t2), (t2, t2), (t2, t1), (t1, phi.data_ptr())]
+    stream = torch.cuda.current_stream().cuda_stream
+    tot = [0.0] * 5
+    for it in range(steps + 1):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record()
+        for k in range(5):
+            S.ps_debug_pass(s.plan, k, io[k][0], io[k][1], stream)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        if it == 0:
+            continue  # warm-up
+        for k in range(5):
+            tot[k] += ev[k].elapsed_time(ev[k + 1])
+    return [t / steps for t in tot]
+
+
+def sampled_error(oracle, rho64, phi, n, ncells, seed=11):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    cells = rng.integers(0, n, (ncells, 3))
+    cells[:3] = [[0, 0, 0], [n - 1, n - 1, n - 1], [n // 2, n // 3, n // 5]]
+    ref = oracle.direct_sum_cells(rho64, cells, 1.0 / n)
+    got = phi[cells[:, 0], cells[:, 1], cells[:, 2]]
+    return float(np.abs(got - ref).max() / np.abs(ref).max()), int(ncells)
+
+
+def cpu_baseline(oracle, n_target: int, n_sample: int):
+    """The oracle's full FFT-convolution solve on a smaller grid, timed on
+    this host, scaled to one solve of the target size by the ratio of FFT
+    work P^3 log2 P (the oracle's cost is dominated by its 1D FFT passes)."""
+    import math
+    from paper_2409_02294_amd import inputs
+    rho = inputs.make_density(n_sample, 64, 1002, sigma=(0.01, 0.05), noise=1e-3)
+    t0 = time.perf_counter()
+    oracle.fft_conv(rho, 1.0 / n_sample)
+    t = time.perf_counter() - t0
+    pt, ps = 2 * n_target, 2 * n_sample
+    ratio = (pt ** 3 * math.log2(pt)) / (ps ** 3 * math.log2(ps))
+    return {
+        "value": 1.0 / (t * ratio),
+        "unit": "solves/s",
+        "cores": oracle.get_threads(),
+        "kind": "oracle",
+        "sample": (f"one full oracle fft_conv solve at {n_sample}^3 (padded {ps}^3, FP64, OpenMP) took {t:.2f} s; "
+                   f"scaled to {n_target}^3 by the FFT-work ratio {ratio:.2f}"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--compare", default="f64,f64_plain", help="other precisions timed beside the headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run one plain 1 GiB device copy (counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the solver has no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2409_02294_amd import inputs
+    from paper_2409_02294_amd import solver as S
+
+    torch.cuda.set_device(0)
+    n = args.n
+    name = {512: "blobs512", 256: "blobs256", 32: "blobs32"}.get(n)
+    t0 = time.perf_counter()
+    log(f"generating the {n}^3 density")
+    rho_np = inputs.workload_density(name) if name else inputs.make_density(n, 64, 1000 + n, noise=1e-3)
+    gen_s = time.perf_counter() - t0
+    log(f"density ready in {gen_s:.1f} s")
+
+    results = {}
+    phis = {}
+    head = args.precision
+    precs = [head] + [p for p in args.compare.split(",") if p and p != head]
+    pass_ms = None
+    for prec in precs:
+        log(f"timing {prec}")
+        try:
+            s = S.Solver(n, 1.0 / n, prec)
+        except S.PSError as e:
+            results[prec] = {"error": str(e)}
+            continue
+        dt = torch.float64 if prec.startswith("f64") else torch.float32
+        rho = torch.from_numpy(rho_np).to("cuda", dt)
+        phi = torch.empty_like(rho)
+        steps = args.steps if prec == head else max(3, args.steps // 4)
+        ms, wall = time_solves(torch, s, rho, phi, steps, args.warmup)
+        rec = {"ms_per_solve": ms, "solves_per_s": 1000.0 / ms, "steps": steps, "wall_s": wall}
+        if prec == head and not prec.endswith("plain"):
+            pass_ms = time_passes(torch, S, s, rho, phi, max(3, steps // 2))
+            rec["pass_ms"] = dict(zip(PASS_NAMES, pass_ms))
+            s(rho, phi)
+        torch.cuda.synchronize()
+        phis[prec] = (phi.double().cpu().numpy(), rho.double().cpu().numpy())
+        results[prec] = rec
+        log(f"{prec}: {rec['ms_per_solve']:.3f} ms/solve")
+        del s, rho, phi
+        torch.cuda.empty_cache()
+
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    hr = results[head]
+    if "error" in hr:
+        print(json.dumps({"metric": METRIC, "error": hr["error"]}))
+        return 1
+    rb = 8 if head.startswith("f64") else 4
+    models = model_bytes(n, rb)
+    ms = hr["ms_per_solve"]
+    out = {
+        "metric": METRIC,
+        "value": hr["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if rb == 8 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{name or 'blobs'}: one {n}^3 free-space solve padded to {2 * n}^3, "
+                        f"{'256' if n == 512 else '64'} Gaussian blobs + 1e-3 noise, resident in HBM",
+            "n": n, "padded": 2 * n, "precision": head,
+        },
+        "effective_GBps_B2": models["B2"] / (ms * 1e-3) / 1e9,
+        "frac_of_peak_B2": models["B2"] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "effective_GBps_B3": models["B3"] / (ms * 1e-3) / 1e9,
+        "bytes_model": models,
+        "others": {k: v for k, v in results.items() if k != head},
+        "input_generation_s": gen_s,
+    }
+    if pass_ms is not None:
+        pb = pass_bytes(n, rb)
+        dom = max(range(5), key=lambda k: pass_ms[k])
+        kname = PASS_NAMES[dom]
+        ach = pb[kname] / (pass_ms[dom] * 1e-3) / 1e9
+        out["pass_ms"] = hr["pass_ms"]
+        out["pass_GBps"] = {PASS_NAMES[k]: pb[PASS_NAMES[k]] / (pass_ms[k] * 1e-3) / 1e9 for k in range(5)}
+        out["roofline"] = {
+            "kernel": kname,
+            "bound": "hbm",
+            "achieved": ach,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS,
+            "traffic": measured_traffic(kname, n, head),
+            "algorithmic_bytes_per_launch": pb[kname],
+            "avg_launch_ms": pass_ms[dom],
+        }
+    for other in ("f64", "f64_plain"):
+        if other in results and "solves_per_s" in results[other]:
+            out[f"speedup_vs_{other}"] = hr["solves_per_s"] / results[other]["solves_per_s"]
+
+    if not args.no_accuracy:
+        import oracle
+        acc = {}
+        for prec, (phi, rho64) in phis.items():
+            log(f"sampled direct sums for {prec}")
+            err, k = sampled_error(oracle, rho64, phi, n, 24)
+            acc[prec] = {"sampled_rel_max_err_vs_direct_sum": err, "cells": k}
+        if "f64" in phis and head in phis and head != "f64":
+            a, ref = phis[head][0], phis["f64"][0]
+            acc[head]["rel_l2_vs_f64_path"] = float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+            acc[head]["rel_max_vs_f64_path"] = float(np.abs(a - ref).max() / np.abs(ref).max())
+        out["accuracy"] = acc
+
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(oracle, n, min(n, 256))
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

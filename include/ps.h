@@ -73,12 +73,17 @@ typedef struct {
     size_t ghat_bytes;      /* bytes of the stored kernel spectrum (real octant) */
     int ready;              /* 1 after a successful ps_green_build */
     int radices[8];         /* forward radix plan, 0-terminated */
+    size_t t1_offset;       /* byte offset in the workspace of T1/T4 (pruned plans; 0 otherwise) */
+    size_t t2_offset;       /* byte offset in the workspace of T2/T3 (pruned plans; 0 otherwise) */
+    int variant[5];         /* kernel variant of each pruned pass (see ps_plan_set_variant) */
 } ps_plan_info;
 
 /* Create a plan for an n^3 grid of spacing dx (> 0) in the given precision.
  * Host work only (radix plan, twiddle tables in double then rounded once to
  * the plan's type, workspace layout); no HIP call.  tune_cache may name a
- * tuning file written by ps_autotune, or be NULL.  On success *out owns a
+ * tuning file written by ps_autotune (its choice for this length and
+ * precision is applied; a missing file or entry keeps the defaults), or be
+ * NULL.  On success *out owns a
  * host object to release with ps_plan_destroy. */
 ps_status ps_plan_create(ps_plan *out, int n, double dx, ps_precision prec, const char *tune_cache);
 
@@ -107,6 +112,21 @@ ps_status ps_solve(ps_plan p, const void *d_rho, void *d_phi, void *stream);
  * (PS_ERR_CAPTURE); later calls with the same list are capture-safe. */
 ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d_rho, void *const *d_phi,
                            void *stream);
+
+/* Choose the kernel variant of one pass of a pruned plan (host only, no HIP
+ * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = radix-32-
+ * based plan (n = 256 and 512 only).  Pass 2 (the fused z pass): 0 =
+ * workgroup-synchronised pencils, 1 = wavefront-owned pencils, 2 =
+ * wavefront-owned pencils on the radix-32-based plan (n = 256, 512).  Every
+ * variant computes the same result to rounding. */
+ps_status ps_plan_set_variant(ps_plan p, int pass, int variant);
+
+/* Time every variant of every pass of a built pruned plan on its own
+ * workspace (contents are overwritten), keep the fastest per pass and, if
+ * cache_path is not NULL, record the choice there for ps_plan_create (a text
+ * file, one line per length and precision).  Synchronises `stream`; not
+ * under stream capture. */
+ps_status ps_autotune(ps_plan p, void *stream, const char *cache_path);
 
 /* Release the host object (the workspace stays the caller's). NULL is a no-op. */
 void ps_plan_destroy(ps_plan p);

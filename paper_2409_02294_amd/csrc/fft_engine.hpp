@@ -24,7 +24,11 @@
 // Butterfly-to-thread mapping per stage: MAP_PF puts the pencil index in the
 // fastest-varying position (lane-contiguous across pencils: coalesced access
 // to arrays whose pencils are interleaved element by element), MAP_EF puts
-// the butterfly index fastest (coalesced access to contiguous pencils).
+// the butterfly index fastest (coalesced access to contiguous pencils), and
+// MAP_WV gives each wavefront its own B / (NT/64) pencils with the butterfly
+// index fastest across the wave's lanes.  When every stage of a transform uses
+// MAP_WV no pencil is shared between wavefronts, and with WSYNC the stage
+// exchanges synchronise the wavefront only, not the workgroup.
 //
 // Twiddles come from a per-plan table computed in double precision on the
 // host and rounded once to T: for stage s >= 1 a row of R entries per
@@ -37,7 +41,7 @@
 
 namespace ps {
 
-enum { MAP_PF = 0, MAP_EF = 1 };
+enum { MAP_PF = 0, MAP_EF = 1, MAP_WV = 2 };
 
 template <int... Rs> struct Radices {
     static constexpr int S = sizeof...(Rs);
@@ -73,8 +77,22 @@ template <int I, int N, class F> __device__ __forceinline__ void static_for(F&& 
     }
 }
 
-template <typename T, class RP, int B, int NT> struct Engine {
+template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine {
     using V = cx<T>;
+    static constexpr int NW = NT / 64;
+    static constexpr int PPW = B / NW;  // pencils per wavefront under MAP_WV
+    static_assert(!WSYNC || (NT % 64 == 0 && B % NW == 0 && PPW >= 1), "wave-owned pencils need B divisible by waves");
+
+    __device__ __forceinline__ static void sync()
+    {
+        if constexpr (WSYNC) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    }
     static constexpr int P = RP::P;
     static constexpr int S = RP::S;
     static constexpr int LP = P + P / 16 + 1;
@@ -95,12 +113,25 @@ template <typename T, class RP, int B, int NT> struct Engine {
         if constexpr (MAP == MAP_PF) {
             p = b % B;
             j = b / B;
-        } else {
+        } else if constexpr (MAP == MAP_EF) {
             j = b % Q<s>;
             p = b / Q<s>;
+        } else {
+            const int i = b / NT, t = b % NT;
+            const int wb = (t & 63) + 64 * i;
+            p = (t >> 6) * PPW + wb / Q<s>;
+            j = wb % Q<s>;
         }
     }
-    template <int s> __device__ __forceinline__ static bool valid(int b) { return FULL<s> || b < BF<s>; }
+    template <int s, int MAP> __device__ __forceinline__ static bool valid(int b)
+    {
+        if constexpr (MAP == MAP_WV) {
+            if constexpr ((PPW * Q<s>) % 64 == 0) return true;
+            else return ((b % NT) & 63) + 64 * (b / NT) < PPW * Q<s>;
+        } else {
+            return FULL<s> || b < BF<s>;
+        }
+    }
 
     // Stage-s twiddles and DFT on the registers of every butterfly this thread owns.
     template <int s, int DIR, int MAP> __device__ __forceinline__ static void compute(Regs<s>& g, const V* __restrict__ tw)
@@ -114,7 +145,7 @@ template <typename T, class RP, int B, int NT> struct Engine {
             if constexpr (NSs > 1) {
                 int p, j;
                 pj<s, MAP>(b, p, j);
-                if (valid<s>(b)) {
+                if (valid<s, MAP>(b)) {
                     const V* row = tw + RP::tw_off(s) + (j % NSs) * Rs;
 #pragma unroll
                     for (int r = 1; r < Rs; ++r) g.v[i][r] = ctw<DIR>(g.v[i][r], row[r]);
@@ -132,7 +163,7 @@ template <typename T, class RP, int B, int NT> struct Engine {
 #pragma unroll
         for (int i = 0; i < NB<s>; ++i) {
             const int b = tid + i * NT;
-            if (!valid<s>(b)) continue;
+            if (!valid<s, MAP>(b)) continue;
             int p, j;
             pj<s, MAP>(b, p, j);
             const int k0 = (j / NSs) * NSs * Rs + (j % NSs);
@@ -148,7 +179,7 @@ template <typename T, class RP, int B, int NT> struct Engine {
 #pragma unroll
         for (int i = 0; i < NB<s>; ++i) {
             const int b = tid + i * NT;
-            if (!valid<s>(b)) {
+            if (!valid<s, MAP>(b)) {
 #pragma unroll
                 for (int r = 0; r < Rs; ++r) g.v[i][r] = V{T(0), T(0)};
                 continue;
@@ -171,7 +202,7 @@ template <typename T, class RP, int B, int NT> struct Engine {
             const int b = tid + i * NT;
             int p, j;
             pj<0, MAP>(b, p, j);
-            const bool ok = valid<0>(b);
+            const bool ok = valid<0, MAP>(b);
             static_for<0, Rs>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
                 const int idx = j + r * Qs;
@@ -196,7 +227,7 @@ template <typename T, class RP, int B, int NT> struct Engine {
 #pragma unroll
         for (int i = 0; i < NB<s>; ++i) {
             const int b = tid + i * NT;
-            if (!valid<s>(b)) continue;
+            if (!valid<s, MAP>(b)) continue;
             int p, j;
             pj<s, MAP>(b, p, j);
             static_for<0, Rs>([&](auto rc) {
@@ -217,10 +248,10 @@ template <typename T, class RP, int B, int NT> struct Engine {
     {
         if constexpr (s < S1) {
             Regs<s> g;
-            __syncthreads();
+            sync();
             load_lds<s, MAP>(g, lds);
             compute<s, DIR, MAP>(g, tw);
-            __syncthreads();
+            sync();
             store_lds<s, MAP>(g, lds);
             middle<s + 1, S1, DIR, MAP>(lds, tw);
         }
@@ -237,15 +268,15 @@ template <typename T, class RP, int B, int NT> struct Engine {
             load_first<MAP_IN, LIN>(g, ld);
             compute<0, DIR, MAP_IN>(g, tw);
             if constexpr (MAP_IN == MAP_OUT) {
-                if constexpr (DST_LDS) __syncthreads();
+                if constexpr (DST_LDS) sync();
                 store_last<MAP_OUT, LOUT>(g, st);
             } else {
                 // one stage but different access patterns on the two sides:
                 // go through LDS in natural order
                 static_assert(!DST_LDS, "LDS destination needs matching mappings");
-                __syncthreads();
+                sync();
                 store_lds<0, MAP_IN>(g, lds);
-                __syncthreads();
+                sync();
                 for (int e = threadIdx.x; e < B * LOUT; e += NT) {
                     int p, idx;
                     if constexpr (MAP_OUT == MAP_PF) {
@@ -263,16 +294,16 @@ template <typename T, class RP, int B, int NT> struct Engine {
                 Regs<0> g;
                 load_first<MAP_IN, LIN>(g, ld);
                 compute<0, DIR, MAP_IN>(g, tw);
-                __syncthreads();
+                sync();
                 store_lds<0, MAP_IN>(g, lds);
             }
             middle<1, S - 1, DIR, MAP_MID>(lds, tw);
             {
                 Regs<S - 1> g;
-                __syncthreads();
+                sync();
                 load_lds<S - 1, MAP_OUT>(g, lds);
                 compute<S - 1, DIR, MAP_OUT>(g, tw);
-                if constexpr (DST_LDS) __syncthreads();
+                if constexpr (DST_LDS) sync();
                 store_last<MAP_OUT, LOUT>(g, st);
             }
         }
@@ -292,11 +323,11 @@ template <typename T, class RP, int B, int NT> struct Engine {
                 Regs<0> g;
                 load_first<MAP_IN, LIN>(g, ld);
                 compute<0, DIR, MAP_IN>(g, tw);
-                __syncthreads();
+                sync();
                 store_lds<0, MAP_IN>(g, lds);
             }
             middle<1, S - 1, DIR, MAP_MID>(lds, tw);
-            __syncthreads();
+            sync();
             load_lds<S - 1, MAP_OUT>(out, lds);
             compute<S - 1, DIR, MAP_OUT>(out, tw);
         }
@@ -313,12 +344,12 @@ template <typename T, class RP, int B, int NT> struct Engine {
             store_last<MAP_OUT, LOUT>(g, st);
         } else {
             compute<0, DIR, MAP_IN>(g, tw);
-            __syncthreads();
+            sync();
             store_lds<0, MAP_IN>(g, lds);
             middle<1, S - 1, DIR, MAP_MID>(lds, tw);
             {
                 Regs<S - 1> h;
-                __syncthreads();
+                sync();
                 load_lds<S - 1, MAP_OUT>(h, lds);
                 compute<S - 1, DIR, MAP_OUT>(h, tw);
                 store_last<MAP_OUT, LOUT>(h, st);

@@ -40,12 +40,12 @@ __device__ __forceinline__ int z_pencil_ky(int q, int N)
 // ---------------------------------------------------------------------------
 // x_r2c: 16 rows (8 packed pairs) of one z-plane per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int NT, int MAP_MID>
 __global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ rho, cx<T>* __restrict__ t1,
                                               const cx<T>* __restrict__ tw)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P>::Fwd, 8, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, 8, NT>;
     constexpr int N = P / 2, H = N + 1;
     __shared__ V lds[E::LDS_ELEMS];
     const int y0 = blockIdx.x * 16;
@@ -80,12 +80,12 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ rho, cx<T>* 
 // ---------------------------------------------------------------------------
 // y_fwd: ZT z-pencils of one kx per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int ZT, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* __restrict__ t1, cx<T>* __restrict__ t2,
                                               const cx<T>* __restrict__ tw)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P>::Fwd, ZT, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ZT, NT>;
     constexpr int N = P / 2;
     __shared__ V lds[E::LDS_ELEMS];
     const int z0 = blockIdx.x * ZT;
@@ -103,14 +103,18 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* __restrict__ t1, cx<T
 
 // ---------------------------------------------------------------------------
 // z_conv: B z-pencils (ky pencils of one kx) per workgroup, in place.
+// WAVE: each wavefront owns its pencils for the whole transform and the stage
+// exchanges synchronise the wavefront only.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int B, int NT, int MAP_MID, int MAP_Z>
+template <typename T, int P, int FAM, int B, int NT, bool WAVE>
 __global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* __restrict__ ghat,
                                                const cx<T>* __restrict__ twf, const cx<T>* __restrict__ twi)
 {
     using V = cx<T>;
-    using EF = Engine<T, typename PlanFor<P>::Fwd, B, NT>;
-    using EI = Engine<T, typename PlanFor<P>::Inv, B, NT>;
+    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE>;
+    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE>;
+    constexpr int MAP_IO = WAVE ? MAP_WV : MAP_EF;
+    constexpr int MAP_MID = MAP_IO, MAP_Z = MAP_IO;
     static_assert(EF::LDS_ELEMS == EI::LDS_ELEMS, "plans share one LDS buffer");
     constexpr int N = P / 2, H = N + 1;
     constexpr int SL = EF::S - 1;
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* 
     V* base = t2 + (size_t)kx * P * N;
     auto ld = [&](int p, int idx) -> V { return base[(size_t)z_pencil_ky(q0 + p, N) * N + idx]; };
     typename EF::template Regs<SL> g;
-    EF::template run_to_regs<-1, MAP_EF, MAP_MID, MAP_Z, N>(lds, twf, ld, g);
+    EF::template run_to_regs<-1, MAP_IO, MAP_MID, MAP_Z, N>(lds, twf, ld, g);
     // multiply by the real, even transformed kernel at (kz, ky, kx)
     {
         constexpr int R = EF::template R<SL>;
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* 
 #pragma unroll
         for (int i = 0; i < EF::template NB<SL>; ++i) {
             const int b = threadIdx.x + i * NT;
-            if (!EF::template valid<SL>(b)) continue;
+            if (!EF::template valid<SL, MAP_Z>(b)) continue;
             int p, j;
             EF::template pj<SL, MAP_Z>(b, p, j);
             const int ky = z_pencil_ky(q0 + p, N);
@@ -144,18 +148,18 @@ __global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* 
         }
     }
     auto st = [&](int p, int idx, V v) { base[(size_t)z_pencil_ky(q0 + p, N) * N + idx] = v; };
-    EI::template run_from_regs<+1, MAP_Z, MAP_MID, MAP_EF, N>(lds, twi, g, st);
+    EI::template run_from_regs<+1, MAP_Z, MAP_MID, MAP_IO, N>(lds, twi, g, st);
 }
 
 // ---------------------------------------------------------------------------
 // y_inv: ZT z-pencils of one kx per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int ZT, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID>
 __global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* __restrict__ t2, cx<T>* __restrict__ t1,
                                               const cx<T>* __restrict__ tw)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P>::Inv, ZT, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT>;
     constexpr int N = P / 2;
     __shared__ V lds[E::LDS_ELEMS];
     const int z0 = blockIdx.x * ZT;
@@ -174,12 +178,12 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* __restrict__ t2, cx<T
 // ---------------------------------------------------------------------------
 // x_c2r: 16 rows (8 packed pairs) of one z-plane per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int NT, int MAP_MID>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ t1, T* __restrict__ phi,
                                               const cx<T>* __restrict__ tw)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P>::Inv, 8, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT>;
     constexpr int N = P / 2, H = N + 1;
     constexpr int XP = H + 1;  // pitch of the staged half spectra
     constexpr int LDS = E::LDS_ELEMS > 16 * XP ? E::LDS_ELEMS : 16 * XP;

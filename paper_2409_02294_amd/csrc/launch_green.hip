@@ -50,8 +50,15 @@ hipError_t green_run(int P, const GreenBufs& b)
 
 template <class RP> static void rlist(std::vector<int>& v) { v.assign(RP::r, RP::r + RP::S); }
 
-bool host_radices(int P, std::vector<int>& fwd)
+bool has_family1(int P) { return P == 512 || P == 1024; }
+
+bool host_radices(int P, std::vector<int>& fwd, int fam)
 {
+    if (fam == 1 && has_family1(P)) {
+        if (P == 512) rlist<PlanFor<512, 1>::Fwd>(fwd);
+        else rlist<PlanFor<1024, 1>::Fwd>(fwd);
+        return true;
+    }
     switch (P) {
 #define PS_CASE(PP) \
     case PP: rlist<PlanFor<PP>::Fwd>(fwd); return true;

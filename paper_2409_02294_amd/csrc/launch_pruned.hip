@@ -1,4 +1,5 @@
-// Launchers of the pruned pipeline for float and double, every supported P.
+// Launchers of the pruned pipeline for float and double, every supported P,
+// with the per-plan kernel variant.
 #include "k_pruned.hpp"
 #include "ps_internal.hpp"
 
@@ -9,37 +10,85 @@ template <typename T> struct PrunedShape {
     static constexpr int ZB = 4;                        // pencils per z-pass workgroup
 };
 
+// Threads of a workgroup whose B pencils are each owned by one wavefront
+// holding >= E elements per lane (several pencils per wave for short P).
+constexpr int wave_threads(int B, int P, int E)
+{
+    int ppw = (64 * E) / P;
+    if (ppw < 1) ppw = 1;
+    if (ppw > B) ppw = B;
+    return 64 * (B / ppw);
+}
+
+template <typename T, int P, int FAM> struct PassLaunch {
+    using V = cx<T>;
+    static constexpr int N = P / 2, H = N + 1;
+    static constexpr int ZT = PrunedShape<T>::ZT, ZB = PrunedShape<T>::ZB;
+    static constexpr int E = FAM == 1 ? 32 : 16;
+    static constexpr int NTX = threads_for(8, P, E);
+    static constexpr int NTY = threads_for(ZT, P, E);
+
+    static void x_r2c(const PrunedBufs& b, const V* tw)
+    {
+        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTX, MAP_EF>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
+                           static_cast<const T*>(b.rho), static_cast<V*>(b.t1), tw);
+    }
+    static void y_fwd(const PrunedBufs& b, const V* tw)
+    {
+        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0, b.stream,
+                           static_cast<const V*>(b.t1), static_cast<V*>(b.t2), tw);
+    }
+    template <bool WAVE> static void z_conv(const PrunedBufs& b, const V* twf, const V* twi)
+    {
+        constexpr int NTZ = WAVE ? wave_threads(ZB, P, E) : threads_for(ZB, P, E);
+        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE>), dim3(P / ZB, H), dim3(NTZ), 0, b.stream,
+                           static_cast<V*>(b.t2), static_cast<const T*>(b.ghat), twf, twi);
+    }
+    static void y_inv(const PrunedBufs& b, const V* tw)
+    {
+        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0, b.stream,
+                           static_cast<const V*>(b.t2), static_cast<V*>(b.t1), tw);
+    }
+    static void x_c2r(const PrunedBufs& b, const V* tw)
+    {
+        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
+                           static_cast<const V*>(b.t1), static_cast<T*>(b.phi), tw);
+    }
+};
+
 template <typename T, int P> static hipError_t pruned_passes(int lo, int hi, const PrunedBufs& b)
 {
     using V = cx<T>;
-    constexpr int N = P / 2, H = N + 1;
-    constexpr int ZT = PrunedShape<T>::ZT, ZB = PrunedShape<T>::ZB;
-    constexpr int NTX = threads_for(8, P);
-    constexpr int NTY = threads_for(ZT, P);
-    constexpr int NTZ = threads_for(ZB, P);
-    const V* twf = static_cast<const V*>(b.twf);
-    const V* twi = static_cast<const V*>(b.twi);
+    using L0 = PassLaunch<T, P, 0>;
+    constexpr bool F1 = has_fam1<P>();
+    using L1 = PassLaunch<T, P, F1 ? 1 : 0>;
+    const V* twf0 = static_cast<const V*>(b.twf);
+    const V* twi0 = static_cast<const V*>(b.twi);
+    const V* twf1 = static_cast<const V*>(F1 ? b.twf1 : b.twf);
+    const V* twi1 = static_cast<const V*>(F1 ? b.twi1 : b.twi);
+    const PrunedVariant& v = b.var;
     for (int pass = lo; pass < hi; ++pass) {
         switch (pass) {
         case 0:
-            hipLaunchKernelGGL((k_x_r2c<T, P, NTX, MAP_EF>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
-                               static_cast<const T*>(b.rho), static_cast<V*>(b.t1), twf);
+            if (v.x_fam == 1 && F1) L1::x_r2c(b, twf1);
+            else L0::x_r2c(b, twf0);
             break;
         case 1:
-            hipLaunchKernelGGL((k_y_fwd<T, P, ZT, NTY, MAP_EF>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0, b.stream,
-                               static_cast<const V*>(b.t1), static_cast<V*>(b.t2), twf);
+            if (v.y_fam == 1 && F1) L1::y_fwd(b, twf1);
+            else L0::y_fwd(b, twf0);
             break;
         case 2:
-            hipLaunchKernelGGL((k_z_conv<T, P, ZB, NTZ, MAP_EF, MAP_EF>), dim3(P / ZB, H), dim3(NTZ), 0, b.stream,
-                               static_cast<V*>(b.t2), static_cast<const T*>(b.ghat), twf, twi);
+            if (v.zmode == 2 && F1) L1::template z_conv<true>(b, twf1, twi1);
+            else if (v.zmode >= 1) L0::template z_conv<true>(b, twf0, twi0);
+            else L0::template z_conv<false>(b, twf0, twi0);
             break;
         case 3:
-            hipLaunchKernelGGL((k_y_inv<T, P, ZT, NTY, MAP_EF>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0, b.stream,
-                               static_cast<const V*>(b.t2), static_cast<V*>(b.t1), twi);
+            if (v.yi_fam == 1 && F1) L1::y_inv(b, twi1);
+            else L0::y_inv(b, twi0);
             break;
         case 4:
-            hipLaunchKernelGGL((k_x_c2r<T, P, NTX, MAP_EF>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
-                               static_cast<const V*>(b.t1), static_cast<T*>(b.phi), twi);
+            if (v.xc_fam == 1 && F1) L1::x_c2r(b, twi1);
+            else L0::x_c2r(b, twi0);
             break;
         default:
             return hipErrorInvalidValue;

@@ -11,48 +11,35 @@
 
 namespace ps {
 
-template <int P> struct PlanFor;
-template <> struct PlanFor<16> { using Fwd = Radices<16>; using Inv = Radices<16>; };
-template <> struct PlanFor<32> { using Fwd = Radices<16, 2>; using Inv = Radices<2, 16>; };
-template <> struct PlanFor<48> { using Fwd = Radices<16, 3>; using Inv = Radices<3, 16>; };
-template <> struct PlanFor<64> { using Fwd = Radices<16, 4>; using Inv = Radices<4, 16>; };
-template <> struct PlanFor<96> { using Fwd = Radices<16, 3, 2>; using Inv = Radices<2, 3, 16>; };
-template <> struct PlanFor<128> { using Fwd = Radices<16, 8>; using Inv = Radices<8, 16>; };
-template <> struct PlanFor<192> { using Fwd = Radices<16, 3, 4>; using Inv = Radices<4, 3, 16>; };
-template <> struct PlanFor<256> { using Fwd = Radices<16, 16>; using Inv = Radices<16, 16>; };
-template <> struct PlanFor<384> { using Fwd = Radices<16, 3, 8>; using Inv = Radices<8, 3, 16>; };
-template <> struct PlanFor<512> { using Fwd = Radices<16, 2, 16>; using Inv = Radices<16, 2, 16>; };
-template <> struct PlanFor<768> { using Fwd = Radices<16, 3, 16>; using Inv = Radices<16, 3, 16>; };
-template <> struct PlanFor<1024> { using Fwd = Radices<16, 4, 16>; using Inv = Radices<16, 4, 16>; };
+// Family 0: radix 16 first, the remaining factors, the inverse reversed.
+template <int P, int FAM = 0> struct PlanFor;
+template <> struct PlanFor<16, 0> { using Fwd = Radices<16>; using Inv = Radices<16>; };
+template <> struct PlanFor<32, 0> { using Fwd = Radices<16, 2>; using Inv = Radices<2, 16>; };
+template <> struct PlanFor<48, 0> { using Fwd = Radices<16, 3>; using Inv = Radices<3, 16>; };
+template <> struct PlanFor<64, 0> { using Fwd = Radices<16, 4>; using Inv = Radices<4, 16>; };
+template <> struct PlanFor<96, 0> { using Fwd = Radices<16, 3, 2>; using Inv = Radices<2, 3, 16>; };
+template <> struct PlanFor<128, 0> { using Fwd = Radices<16, 8>; using Inv = Radices<8, 16>; };
+template <> struct PlanFor<192, 0> { using Fwd = Radices<16, 3, 4>; using Inv = Radices<4, 3, 16>; };
+template <> struct PlanFor<256, 0> { using Fwd = Radices<16, 16>; using Inv = Radices<16, 16>; };
+template <> struct PlanFor<384, 0> { using Fwd = Radices<16, 3, 8>; using Inv = Radices<8, 3, 16>; };
+template <> struct PlanFor<512, 0> { using Fwd = Radices<16, 2, 16>; using Inv = Radices<16, 2, 16>; };
+template <> struct PlanFor<768, 0> { using Fwd = Radices<16, 3, 16>; using Inv = Radices<16, 3, 16>; };
+template <> struct PlanFor<1024, 0> { using Fwd = Radices<16, 4, 16>; using Inv = Radices<16, 4, 16>; };
 
-// Threads for B pencils of length P at ~16 elements per thread, whole waves.
-constexpr int threads_for(int B, int P)
+// Family 1: radix 32 first, one stage fewer (one LDS exchange fewer per
+// transform) where P allows it.
+template <int P> constexpr bool has_fam1() { return P == 512 || P == 1024; }
+template <> struct PlanFor<512, 1> { using Fwd = Radices<32, 16>; using Inv = Radices<16, 32>; };
+template <> struct PlanFor<1024, 1> { using Fwd = Radices<32, 32>; using Inv = Radices<32, 32>; };
+
+// Threads for B pencils of length P at ~E elements per thread, whole waves.
+constexpr int threads_for(int B, int P, int E = 16)
 {
-    int t = B * P / 16;
+    int t = B * P / E;
     t = (t + 63) / 64 * 64;
     if (t < 64) t = 64;
     if (t > 1024) t = 1024;
     return t;
-}
-
-// Apply F<P>() for the runtime P; returns false if P is not supported.
-template <template <int> class F, class... A> bool dispatch_p(int P, A&&... a)
-{
-    switch (P) {
-    case 16: F<16>::run(a...); return true;
-    case 32: F<32>::run(a...); return true;
-    case 48: F<48>::run(a...); return true;
-    case 64: F<64>::run(a...); return true;
-    case 96: F<96>::run(a...); return true;
-    case 128: F<128>::run(a...); return true;
-    case 192: F<192>::run(a...); return true;
-    case 256: F<256>::run(a...); return true;
-    case 384: F<384>::run(a...); return true;
-    case 512: F<512>::run(a...); return true;
-    case 768: F<768>::run(a...); return true;
-    case 1024: F<1024>::run(a...); return true;
-    default: return false;
-    }
 }
 
 }  // namespace ps

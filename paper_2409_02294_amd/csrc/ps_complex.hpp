@@ -159,6 +159,53 @@ template <int DIR, typename V> __device__ __forceinline__ void dft16(V* v)
     }
 }
 
+// a * exp(DIR * 2 pi i * M / 32), M odd in [1, 16): constants cos/sin(M pi / 16)
+template <int DIR, int M, typename V> __device__ __forceinline__ V w32(V a)
+{
+    using T = decltype(a.x);
+    if constexpr (M % 2 == 0) return w16<DIR, M / 2>(a);
+    else {
+        // cos(k pi/16), k = 1, 3, 5, ..., 15
+        constexpr double C[8] = {0.98078528040323044913, 0.83146961230254523708, 0.55557023301960222474,
+                                 0.19509032201612826785, -0.19509032201612826785, -0.55557023301960222474,
+                                 -0.83146961230254523708, -0.98078528040323044913};
+        constexpr double S[8] = {0.19509032201612826785, 0.55557023301960222474, 0.83146961230254523708,
+                                 0.98078528040323044913, 0.98078528040323044913, 0.83146961230254523708,
+                                 0.55557023301960222474, 0.19509032201612826785};
+        constexpr double cr = C[M / 2];
+        constexpr double ci = DIR < 0 ? -S[M / 2] : S[M / 2];
+        const T c = T(cr), s = T(ci);
+        return V{a.x * c - a.y * s, a.x * s + a.y * c};
+    }
+}
+
+template <int DIR, int K = 1, typename V> __device__ __forceinline__ void static_for32(V* o)
+{
+    if constexpr (K < 16) {
+        o[K] = w32<DIR, K>(o[K]);
+        static_for32<DIR, K + 1>(o);
+    }
+}
+
+// 32 = 2 x 16 (decimation in time): X[k] = E[k] + w^k O[k], X[k+16] = E[k] - w^k O[k].
+template <int DIR, typename V> __device__ __forceinline__ void dft32(V* v)
+{
+    V e[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        e[i] = v[2 * i];
+        o[i] = v[2 * i + 1];
+    }
+    dft16<DIR>(e);
+    dft16<DIR>(o);
+    static_for32<DIR>(o);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = cadd(e[k], o[k]);
+        v[k + 16] = csub(e[k], o[k]);
+    }
+}
+
 template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
 {
     if constexpr (R == 1) {
@@ -167,6 +214,7 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
     else if constexpr (R == 4) dft4<DIR>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
+    else if constexpr (R == 32) dft32<DIR>(v);
     else static_assert(R == 2, "unsupported radix");
 }
 

@@ -7,10 +7,14 @@
 // validates them before any HIP call and reports a status code.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -130,6 +134,8 @@ struct ps_plan_s {
     std::vector<unsigned char> tables;
     size_t off_tab = 0, tab_bytes = 0;
     size_t tw_f = 0, tw_i = 0, tw_f64 = 0;  // offsets inside the table blob
+    size_t tw_f1 = 0, tw_i1 = 0;            // family-1 plan tables
+    ps::PrunedVariant var;                  // kernel variant per pass
     size_t off_ghat = 0, ghat_bytes = 0;
     size_t off_t1 = 0, off_t2 = 0;          // pruned intermediates
     size_t off_pad = 0, off_spec = 0;       // plain intermediates
@@ -159,8 +165,79 @@ ps::PrunedBufs pruned_bufs(ps_plan p, const void* rho, void* phi, hipStream_t s)
     b.ghat = p->ws + p->off_ghat;
     b.twf = p->ws + p->off_tab + p->tw_f;
     b.twi = p->ws + p->off_tab + p->tw_i;
+    b.twf1 = p->ws + p->off_tab + p->tw_f1;
+    b.twi1 = p->ws + p->off_tab + p->tw_i1;
+    b.var = p->var;
     b.stream = s;
     return b;
+}
+
+const char* prec_name(ps_precision p)
+{
+    switch (p) {
+    case PS_F64: return "f64";
+    case PS_F32: return "f32";
+    case PS_F32_SPLIT: return "f32_split";
+    case PS_F64_PLAIN: return "f64_plain";
+    case PS_F32_PLAIN: return "f32_plain";
+    }
+    return "?";
+}
+
+int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : 2; }
+
+int* variant_slot(ps::PrunedVariant& v, int pass)
+{
+    switch (pass) {
+    case 0: return &v.x_fam;
+    case 1: return &v.y_fam;
+    case 2: return &v.zmode;
+    case 3: return &v.yi_fam;
+    default: return &v.xc_fam;
+    }
+}
+
+// Tuning cache: one line per (P, precision): "P prec x y z yi xc".
+bool read_tuning(const char* path, int P, ps_precision prec, ps::PrunedVariant& v)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        int pp;
+        std::string pr;
+        ps::PrunedVariant t;
+        if (!(is >> pp >> pr >> t.x_fam >> t.y_fam >> t.zmode >> t.yi_fam >> t.xc_fam)) continue;
+        if (pp == P && pr == prec_name(prec)) {
+            v = t;  // the last matching line wins
+            found = true;
+        }
+    }
+    return found;
+}
+
+bool write_tuning(const char* path, int P, ps_precision prec, const ps::PrunedVariant& v)
+{
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            std::istringstream is(line);
+            int pp;
+            std::string pr;
+            if ((is >> pp >> pr) && pp == P && pr == prec_name(prec)) continue;
+            if (!line.empty()) keep.push_back(line);
+        }
+    }
+    std::ofstream o(path, std::ios::trunc);
+    if (!o) return false;
+    for (auto& l : keep) o << l << "\n";
+    o << P << " " << prec_name(prec) << " " << v.x_fam << " " << v.y_fam << " " << v.zmode << " " << v.yi_fam << " "
+      << v.xc_fam << "\n";
+    return (bool)o;
 }
 
 }  // namespace
@@ -184,7 +261,6 @@ const char* ps_last_error(void) { return g_last_error.c_str(); }
 
 ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, const char* tune_cache)
 {
-    (void)tune_cache;
     if (!out) return fail(PS_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(PS_ERR_INVALID, "dx must be positive and finite");
@@ -194,7 +270,7 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     if (!supported_n(n))
         return fail(PS_ERR_UNSUPPORTED, "n = " + std::to_string(n) +
                                             " unsupported (2n must be 2^a or 3*2^a with 16 <= 2n <= 1024)");
-    if (prec == PS_F32_SPLIT || is_plain(prec))
+    if (prec == PS_F32_SPLIT)
         return fail(PS_ERR_UNSUPPORTED, "precision " + std::to_string((int)prec) + " is not built into this library");
     ps_plan p = new (std::nothrow) ps_plan_s();
     if (!p) return fail(PS_ERR_INVALID, "out of host memory");
@@ -210,15 +286,31 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     }
     const std::vector<int> inv(p->radices.rbegin(), p->radices.rend());
     const auto tf = plan_table(p->radices), ti = plan_table(inv);
+    std::vector<int> fwd1;
+    ps::host_radices(p->P, fwd1, 1);
+    const std::vector<int> inv1(fwd1.rbegin(), fwd1.rend());
+    const auto tf1 = plan_table(fwd1), ti1 = plan_table(inv1);
     if (is_f64(prec)) {
         append_table<double>(p->tables, p->tw_f, tf);
         append_table<double>(p->tables, p->tw_i, ti);
+        append_table<double>(p->tables, p->tw_f1, tf1);
+        append_table<double>(p->tables, p->tw_i1, ti1);
         p->tw_f64 = p->tw_f;
     } else {
         append_table<float>(p->tables, p->tw_f, tf);
         append_table<float>(p->tables, p->tw_i, ti);
+        append_table<float>(p->tables, p->tw_f1, tf1);
+        append_table<float>(p->tables, p->tw_i1, ti1);
         append_table<double>(p->tables, p->tw_f64, tf);
     }
+    // default variants: wave-owned z pass; family 1 where it exists
+    if (ps::has_family1(p->P)) {
+        p->var.x_fam = p->var.y_fam = p->var.yi_fam = p->var.xc_fam = 1;
+        p->var.zmode = 2;
+    } else {
+        p->var.zmode = 1;
+    }
+    if (tune_cache && !is_plain(prec)) read_tuning(tune_cache, p->P, prec, p->var);
     const size_t N = n, P = p->P, H = p->H, r = p->real_bytes, c = 2 * r;
     size_t off = 0;
     p->off_tab = off;
@@ -271,6 +363,11 @@ ps_status ps_plan_query(ps_plan p, ps_plan_info* info)
     info->ghat_bytes = p->ghat_bytes;
     info->ready = p->ready ? 1 : 0;
     for (size_t i = 0; i < p->radices.size() && i < 7; ++i) info->radices[i] = p->radices[i];
+    if (!is_plain(p->prec)) {
+        info->t1_offset = p->off_t1;
+        info->t2_offset = p->off_t2;
+        for (int k = 0; k < 5; ++k) info->variant[k] = *variant_slot(p->var, k);
+    }
     return PS_OK;
 }
 
@@ -372,6 +469,74 @@ ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void
     hipError_t e = is_f64(p->prec) ? ps::pruned_run_f64(p->P, pass, pass + 1, b)
                                    : ps::pruned_run_f32(p->P, pass, pass + 1, b);
     if (e != hipSuccess) return device_fail(e, "pass launch");
+    return PS_OK;
+}
+
+ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (is_plain(p->prec)) return fail(PS_ERR_UNSUPPORTED, "plain plans have no variants");
+    if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..4");
+    if (variant < 0 || variant >= num_variants(pass)) return fail(PS_ERR_INVALID, "variant out of range");
+    const bool needs_f1 = (pass == 2) ? variant == 2 : variant == 1;
+    if (needs_f1 && !ps::has_family1(p->P))
+        return fail(PS_ERR_UNSUPPORTED, "this length has no radix-32 plan family");
+    *variant_slot(p->var, pass) = variant;
+    return PS_OK;
+}
+
+ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (is_plain(p->prec)) return fail(PS_ERR_UNSUPPORTED, "plain plans have no variants");
+    if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
+    hipStream_t st = (hipStream_t)stream;
+    bool cap = false;
+    hipError_t e;
+    if (!capturing(st, cap, e)) return device_fail(e, "hipStreamIsCapturing");
+    if (cap) return fail(PS_ERR_CAPTURE, "ps_autotune cannot run under stream capture");
+    // rho and phi stand-ins: the start of T2, which passes 0 and 4 do not touch
+    ps::PrunedBufs b = pruned_bufs(p, p->ws + p->off_t2, p->ws + p->off_t2, st);
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return device_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        hipEventDestroy(e0);
+        return device_fail(e, "hipEventCreate");
+    }
+    ps_status rc = PS_OK;
+    ps::PrunedVariant best = p->var;
+    for (int pass = 0; pass < 5 && rc == PS_OK; ++pass) {
+        float best_ms = 1e30f;
+        for (int v = 0; v < num_variants(pass); ++v) {
+            const bool needs_f1 = (pass == 2) ? v == 2 : v == 1;
+            if (needs_f1 && !ps::has_family1(p->P)) continue;
+            *variant_slot(b.var, pass) = v;
+            const int reps = 5;
+            float ms = 0.f;
+            for (int r = 0; r <= reps && rc == PS_OK; ++r) {
+                hipEventRecord(e0, st);
+                e = is_f64(p->prec) ? ps::pruned_run_f64(p->P, pass, pass + 1, b)
+                                    : ps::pruned_run_f32(p->P, pass, pass + 1, b);
+                hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float t = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+                if (e != hipSuccess) rc = device_fail(e, "autotune");
+                if (r > 0) ms += t;  // the first run is a warm-up
+            }
+            if (rc == PS_OK && ms < best_ms) {
+                best_ms = ms;
+                *variant_slot(best, pass) = v;
+            }
+        }
+        *variant_slot(b.var, pass) = *variant_slot(best, pass);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != PS_OK) return rc;
+    p->var = best;
+    if (cache_path && !write_tuning(cache_path, p->P, p->prec, best))
+        return fail(PS_ERR_INVALID, std::string("cannot write tuning cache ") + cache_path);
     return PS_OK;
 }
 

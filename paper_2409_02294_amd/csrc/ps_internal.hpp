@@ -11,6 +11,15 @@
 
 namespace ps {
 
+// Kernel variants of the pruned pipeline (chosen per plan, e.g. by the
+// autotuner).  fam: radix-plan family (0: radix-16 based, 1: radix-32 based
+// where P allows it, else 0).  zmode: 0 workgroup-synchronised z pass,
+// 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1).
+struct PrunedVariant {
+    int x_fam = 0, y_fam = 0, zmode = 0, yi_fam = 0, xc_fam = 0;
+};
+constexpr int NUM_ZMODES = 3;
+
 // Device buffers of one solve of the pruned pipeline.  Complex arrays are
 // interleaved (re, im) of the plan's real type.
 struct PrunedBufs {
@@ -19,8 +28,11 @@ struct PrunedBufs {
     void* t1;          // [H][N][N] complex
     void* t2;          // [H][P][N] complex
     const void* ghat;  // [H][H][H] real octant, scaled
-    const void* twf;   // forward-plan twiddles
-    const void* twi;   // inverse-plan twiddles
+    const void* twf;   // forward-plan twiddles, family 0
+    const void* twi;   // inverse-plan twiddles, family 0
+    const void* twf1;  // forward-plan twiddles, family 1
+    const void* twi1;  // inverse-plan twiddles, family 1
+    PrunedVariant var;
     hipStream_t stream;
 };
 
@@ -55,7 +67,9 @@ struct PlainBufs {
 hipError_t plain_run_f32(int P, const PlainBufs& b);
 hipError_t plain_run_f64(int P, const PlainBufs& b);
 
-// Radix plans (forward; the inverse is the reverse) for a supported P.
-bool host_radices(int P, std::vector<int>& fwd);
+// Radix plans (forward; the inverse is the reverse) for a supported P and
+// plan family; family 1 falls back to family 0 where it does not exist.
+bool host_radices(int P, std::vector<int>& fwd, int fam = 0);
+bool has_family1(int P);
 
 }  // namespace ps

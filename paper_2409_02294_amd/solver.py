@@ -38,7 +38,8 @@ PRECISIONS = {"f64": PS_F64, "f32": PS_F32, "f32_split": PS_F32_SPLIT,
 SUPPORTED_N = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 EXPORTS = ("ps_plan_create", "ps_plan_workspace_bytes", "ps_plan_query", "ps_green_build", "ps_solve",
-           "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass")
+           "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass",
+           "ps_plan_set_variant", "ps_autotune")
 
 
 class PSError(RuntimeError):
@@ -50,7 +51,8 @@ class PSError(RuntimeError):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("h", ctypes.c_int), ("precision", ctypes.c_int),
                 ("dx", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t), ("ghat_bytes", ctypes.c_size_t),
-                ("ready", ctypes.c_int), ("radices", ctypes.c_int * 8)]
+                ("ready", ctypes.c_int), ("radices", ctypes.c_int * 8),
+                ("t1_offset", ctypes.c_size_t), ("t2_offset", ctypes.c_size_t), ("variant", ctypes.c_int * 5)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -80,6 +82,8 @@ def load() -> ctypes.CDLL:
         "ps_status_str": ([i], ctypes.c_char_p),
         "ps_last_error": ([], ctypes.c_char_p),
         "ps_debug_pass": ([vp, i, vp, vp, vp], i),
+        "ps_plan_set_variant": ([vp, i, i], i),
+        "ps_autotune": ([vp, vp, ctypes.c_char_p], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -122,7 +126,7 @@ def ps_plan_query(plan: int) -> Dict:
     rad = [r for r in info.radices if r]
     return dict(n=info.n, p=info.p, h=info.h, precision=info.precision, dx=info.dx,
                 workspace_bytes=info.workspace_bytes, ghat_bytes=info.ghat_bytes, ready=bool(info.ready),
-                radices=rad)
+                radices=rad, t1_offset=info.t1_offset, t2_offset=info.t2_offset, variant=list(info.variant))
 
 
 def ps_green_build(plan: int, workspace: int, G: float, self_coeff: float, stream: int) -> None:
@@ -148,6 +152,15 @@ def ps_plan_destroy(plan: int) -> None:
 
 def ps_debug_pass(plan: int, pass_id: int, d_in: int, d_out: int, stream: int) -> None:
     _check(load().ps_debug_pass(plan, int(pass_id), d_in, d_out, stream), "ps_debug_pass")
+
+
+def ps_plan_set_variant(plan: int, pass_id: int, variant: int) -> None:
+    _check(load().ps_plan_set_variant(plan, int(pass_id), int(variant)), "ps_plan_set_variant")
+
+
+def ps_autotune(plan: int, stream: int, cache_path: Optional[str] = None) -> None:
+    cp = cache_path.encode() if cache_path else None
+    _check(load().ps_autotune(plan, stream, cp), "ps_autotune")
 
 
 # ---------------------------------------------------------------------------

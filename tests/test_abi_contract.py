@@ -135,3 +135,41 @@ def test_device_errors_are_reported_not_raised():
         assert S.ps_last_error()
     finally:
         S.ps_plan_destroy(p)
+
+
+def test_variant_selection_contract():
+    p = S.ps_plan_create(32, 1.0 / 32, S.PS_F32)
+    q = S.ps_plan_create(256, 1.0 / 256, S.PS_F64)
+    try:
+        lib = S.load()
+        assert lib.ps_plan_set_variant(p, 5, 0) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED  # no radix-32 family at P = 64
+        assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
+        S.ps_plan_set_variant(p, 2, 0)
+        assert S.ps_plan_query(p)["variant"][2] == 0
+        S.ps_plan_set_variant(q, 0, 1)
+        S.ps_plan_set_variant(q, 2, 2)
+        v = S.ps_plan_query(q)["variant"]
+        assert v[0] == 1 and v[2] == 2
+        assert lib.ps_autotune(p, None, None) == S.PS_ERR_NOT_READY
+    finally:
+        S.ps_plan_destroy(p)
+        S.ps_plan_destroy(q)
+
+
+def test_tuning_cache_is_read(tmp_path):
+    path = tmp_path / "tune.txt"
+    path.write_text("64 f32 0 0 0 0 0\n512 f32 0 1 1 0 1\n512 f64 1 1 2 1 1\n")
+    p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32, str(path))
+    try:
+        assert S.ps_plan_query(p)["variant"] == [0, 1, 1, 0, 1]
+    finally:
+        S.ps_plan_destroy(p)
+    # a missing file keeps the defaults
+    p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32, str(tmp_path / "absent.txt"))
+    try:
+        assert S.ps_plan_query(p)["variant"] == [1, 1, 2, 1, 1]
+    finally:
+        S.ps_plan_destroy(p)

@@ -20,7 +20,7 @@ if gpu_available():
     from paper_2409_02294_amd import solver as S
 
 
-TOL = {"f64": 1e-12, "f32": 1e-6}
+TOL = {"f64": 1e-12, "f32": 1e-6, "f64_plain": 1e-12, "f32_plain": 1e-6}
 
 
 def _dtype(prec):
@@ -112,7 +112,7 @@ def test_passes_match_numpy(prec, n):
 # Whole solves against the oracle
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f64_plain", "f32_plain"])
 @pytest.mark.parametrize("n", [8, 16, 24, 32, 48, 64, 96])
 def test_solve_matches_oracle_fft_conv(prec, n):
     rho = inputs.make_density(n, 6, 300 + n, sigma=(0.03, 0.1), noise=1e-3)
@@ -122,7 +122,7 @@ def test_solve_matches_oracle_fft_conv(prec, n):
     assert l2 <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f64_plain", "f32_plain"])
 def test_blobs32_matches_direct_sum(prec):
     rho = inputs.workload_density("blobs32")
     got, rho_used, _ = gpu_solve(rho, prec)
@@ -201,7 +201,7 @@ def test_n128_full_oracle(prec):
     assert l2 <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f64_plain"])
 def test_blobs256_sampled_direct_sum(prec):
     rho = inputs.workload_density("blobs256")
     got, rho_used, _ = gpu_solve(rho, prec)
@@ -211,3 +211,67 @@ def test_blobs256_sampled_direct_sum(prec):
     err = np.abs(g - ref).max() / np.abs(ref).max()
     print(f"blobs256 {prec}: sampled rel max err {err:.3e}", flush=True)
     assert err <= TOL[prec]
+
+
+# ---------------------------------------------------------------------------
+# Kernel variants: every variant of every pass gives the same solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_variants_agree_n256(prec):
+    n = 256
+    rho_np = inputs.make_density(n, 16, 99, sigma=(0.02, 0.06), noise=1e-3)
+    s = S.Solver(n, 1.0 / n, prec)
+    rho = torch.from_numpy(rho_np).to("cuda", _dtype(prec))
+    for k in range(5):
+        S.ps_plan_set_variant(s.plan, k, 0)
+    base = s(rho).double().cpu().numpy()
+    tol = 1e-13 if prec == "f64" else 5e-7
+    for k, nv in zip(range(5), (2, 2, 3, 2, 2)):
+        for v in range(1, nv):
+            S.ps_plan_set_variant(s.plan, k, v)
+            got = s(rho).double().cpu().numpy()
+            l2 = oracle.rel_l2(got, base)
+            print(f"n=256 {prec} pass {k} variant {v}: relL2 vs variant 0 = {l2:.2e}", flush=True)
+            assert l2 <= tol
+        S.ps_plan_set_variant(s.plan, k, 0)
+    # all-defaults result against sampled direct sums
+    for k, v in zip(range(5), (1, 1, 2, 1, 1)):
+        S.ps_plan_set_variant(s.plan, k, v)
+    got = s(rho).double().cpu().numpy()
+    rho64 = rho.double().cpu().numpy()
+    cells = _sample_cells(n, 48, 3)
+    ref = oracle.direct_sum_cells(rho64, cells, 1.0 / n)
+    err = np.abs(got[cells[:, 0], cells[:, 1], cells[:, 2]] - ref).max() / np.abs(ref).max()
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [16, 48, 96])
+@pytest.mark.parametrize("zmode", [0, 1])
+def test_zmodes_match_oracle(prec, n, zmode):
+    rho = inputs.make_density(n, 5, 500 + n, sigma=(0.03, 0.1), noise=1e-3)
+    s = S.Solver(n, 1.0 / n, prec)
+    S.ps_plan_set_variant(s.plan, 2, zmode)
+    r = torch.from_numpy(rho).to("cuda", _dtype(prec))
+    got = s(r).double().cpu().numpy()
+    ref = oracle.fft_conv(r.double().cpu().numpy(), 1.0 / n)
+    l2, _ = _report(f"zmode {zmode} n={n} {prec}", got, ref)
+    assert l2 <= TOL[prec]
+
+
+def test_autotune_writes_cache(tmp_path):
+    n = 64
+    s = S.Solver(n, 1.0 / n, "f32")
+    path = str(tmp_path / "tune.txt")
+    S.ps_autotune(s.plan, torch.cuda.current_stream().cuda_stream, path)
+    lines = open(path).read().split()
+    assert lines[:2] == ["128", "f32"]
+    chosen = s.info()["variant"]
+    s2 = S.Solver(n, 1.0 / n, "f32", tune_cache=path)
+    assert s2.info()["variant"] == chosen
+    rho = inputs.make_density(n, 5, 7, sigma=(0.03, 0.1))
+    r = torch.from_numpy(rho).to("cuda", torch.float32)
+    got = s2(r).double().cpu().numpy()
+    ref = oracle.fft_conv(r.double().cpu().numpy(), 1.0 / n)
+    assert oracle.rel_l2(got, ref) <= 1e-6
