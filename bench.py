@@ -161,9 +161,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--precision", default="f32")
-    ap.add_argument("--compare", default="f64,f64_plain", help="other precisions timed beside the headline")
+    ap.add_argument("--compare", default="f32_split,f64,f64_plain", help="other precisions timed beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel variants")
     ap.add_argument("--copy-probe", action="store_true", help="also run one plain 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
 
@@ -203,9 +204,14 @@ def main() -> int:
         dt = torch.float64 if prec.startswith("f64") else torch.float32
         rho = torch.from_numpy(rho_np).to("cuda", dt)
         phi = torch.empty_like(rho)
+        if not prec.endswith("plain") and not args.no_tune:
+            # the autotuner picks each pass's fastest kernel variant (outside the timed region)
+            S.ps_autotune(s.plan, torch.cuda.current_stream().cuda_stream, None)
         steps = args.steps if prec == head else max(3, args.steps // 4)
         ms, wall = time_solves(torch, s, rho, phi, steps, args.warmup)
         rec = {"ms_per_solve": ms, "solves_per_s": 1000.0 / ms, "steps": steps, "wall_s": wall}
+        if not prec.endswith("plain"):
+            rec["variants"] = s.info()["variant"]
         if prec == head and not prec.endswith("plain"):
             pass_ms = time_passes(torch, S, s, rho, phi, max(3, steps // 2))
             rec["pass_ms"] = dict(zip(PASS_NAMES, pass_ms))

@@ -58,7 +58,8 @@ typedef enum {
 typedef enum {
     PS_F64 = 0,       /* pruned, fused pipeline in double */
     PS_F32 = 1,       /* pruned, fused pipeline in float; kernel and twiddles built in double, rounded once */
-    PS_F32_SPLIT = 2, /* as PS_F32, radix-16 DFTs on bf16 matrix cores with split operands, fp32 accumulation */
+    PS_F32_SPLIT = 2, /* as PS_F32, radix-16 DFTs on bf16 matrix cores (v_mfma_f32_32x32x16_bf16) with split
+                         operands and fp32 accumulation */
     PS_F64_PLAIN = 3, /* the plain method in double: padded grid, full 3D R2C, product, full C2R, crop */
     PS_F32_PLAIN = 4  /* the plain method in float */
 } ps_precision;
@@ -76,6 +77,7 @@ typedef struct {
     size_t t1_offset;       /* byte offset in the workspace of T1/T4 (pruned plans; 0 otherwise) */
     size_t t2_offset;       /* byte offset in the workspace of T2/T3 (pruned plans; 0 otherwise) */
     int variant[5];         /* kernel variant of each pruned pass (see ps_plan_set_variant) */
+    int split_terms;        /* PS_F32_SPLIT: split-bf16 product terms per DFT-16 (6 or 3); else 0 */
 } ps_plan_info;
 
 /* Create a plan for an n^3 grid of spacing dx (> 0) in the given precision.
@@ -118,7 +120,11 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * based plan (n = 256 and 512 only).  Pass 2 (the fused z pass): 0 =
  * workgroup-synchronised pencils, 1 = wavefront-owned pencils, 2 =
  * wavefront-owned pencils on the radix-32-based plan (n = 256, 512).  Every
- * variant computes the same result to rounding. */
+ * variant computes the same result to rounding.  PS_F32_SPLIT plans keep the
+ * radix-16-based plan (variants 0 and 0/1 only); for them "pass" 5 sets the
+ * number of split-bf16 product terms per DFT-16: 6 (three pieces per
+ * operand, all piece products of order <= 2; the default) or 3 (two pieces,
+ * order <= 1). */
 ps_status ps_plan_set_variant(ps_plan p, int pass, int variant);
 
 /* Time every variant of every pass of a built pruned plan on its own

@@ -77,11 +77,107 @@ template <int I, int N, class F> __device__ __forceinline__ void static_for(F&& 
     }
 }
 
-template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine {
+// ---------------------------------------------------------------------------
+// Radix-16 DFTs on the bf16 matrix cores with split operands.
+//
+// A length-16 DFT of 32 pencils at once is the real product
+//   [Re y; Im y] = [[Wr, -Wi], [Wi, Wr]] [Re x; Im x]
+// of a 32 x 32 matrix and a 32 x 32 block (one column per pencil), done as
+// two v_mfma_f32_32x32x16_bf16 per product term (K = 16 real parts, then 16
+// imaginary parts).  Every operand is split into bf16 pieces, x = x0 + x1 + x2
+// with x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1) (each
+// difference is exact in fp32), and the product is summed over the piece
+// pairs of order <= 2 (six terms, MT = 6) or <= 1 with two pieces (three
+// terms, MT = 3), accumulating in fp32.  The matrix pieces are split in double
+// on the host and loaded once per workgroup.
+//
+// Lane layout (wavefront of 64): lane l works on pencil column c = l % 32 and
+// holds elements 8h .. 8h+7 (h = l / 32) of that column's 16 inputs, and
+// after the product the same element indices of the 16 outputs: the matrix
+// rows are permuted so that the accumulator layout of the instruction (lane l
+// holds rows 8j + 4h + i, j, i < 4) lands on outputs 8h + 4(j % 2) + i, real
+// part for j < 2 and imaginary part for j >= 2.  The inverse transform uses
+// conj(DFT(conj x)).
+// ---------------------------------------------------------------------------
+typedef __bf16 ps_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float ps_f32x16 __attribute__((ext_vector_type(16)));
+
+template <int MT> struct SplitA {
+    ps_bf16x8 a[3][2];  // [piece][K chunk: 0 real parts, 1 imaginary parts]
+    // tab: [piece][chunk][lane][8] bf16 bit patterns
+    __device__ __forceinline__ void load(const unsigned short* __restrict__ tab)
+    {
+        const int l = threadIdx.x & 63;
+#pragma unroll
+        for (int pc = 0; pc < 3; ++pc)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                a[pc][c] = *reinterpret_cast<const ps_bf16x8*>(tab + ((pc * 2 + c) * 64 + l) * 8);
+    }
+};
+template <> struct SplitA<0> {
+    __device__ __forceinline__ void load(const unsigned short*) {}
+};
+
+template <int NP> __device__ __forceinline__ void split_pieces(const float* x, ps_bf16x8* out)
+{
+    float r[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = x[i];
+#pragma unroll
+    for (int pc = 0; pc < NP; ++pc) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            out[pc][i] = (__bf16)r[i];
+            r[i] = r[i] - (float)out[pc][i];
+        }
+    }
+}
+
+// In-place forward (DIR -1) or inverse (DIR +1) DFT-16 of the lane's 8 elements.
+template <int MT, int DIR> __device__ __forceinline__ void dft16_split(float2* v, const SplitA<MT>& sa)
+{
+    static_assert(MT == 3 || MT == 6, "3 or 6 product terms");
+    constexpr int NP = MT == 6 ? 3 : 2;
+    float re[8], im[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        re[q] = v[q].x;
+        im[q] = DIR < 0 ? v[q].y : -v[q].y;
+    }
+    ps_bf16x8 br[NP], bi[NP];
+    split_pieces<NP>(re, br);
+    split_pieces<NP>(im, bi);
+    ps_f32x16 acc = {};
+    // smallest terms first
+    if constexpr (MT == 6) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[2][0], br[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[2][1], bi[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[1][0], br[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[1][1], bi[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[0][0], br[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[0][1], bi[2], acc, 0, 0, 0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[1][0], br[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[1][1], bi[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[0][0], br[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[0][1], bi[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[0][0], br[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa.a[0][1], bi[0], acc, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = float2{acc[q], DIR < 0 ? acc[8 + q] : -acc[8 + q]};
+}
+
+// MT: 0 = every stage on the vector ALUs; 3 or 6 = radix-16 stages on the
+// matrix cores with that many split product terms (T = float only).
+template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> struct Engine {
     using V = cx<T>;
+    using SA = SplitA<MT>;
+    static_assert(MT == 0 || std::is_same<T, float>::value, "split matrix-core DFTs are single precision");
     static constexpr int NW = NT / 64;
     static constexpr int PPW = B / NW;  // pencils per wavefront under MAP_WV
     static_assert(!WSYNC || (NT % 64 == 0 && B % NW == 0 && PPW >= 1), "wave-owned pencils need B divisible by waves");
+    static_assert(MT == 0 || NT % 64 == 0, "matrix-core stages need whole wavefronts");
 
     __device__ __forceinline__ static void sync()
     {
@@ -101,12 +197,32 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine
     template <int s> static constexpr int R = RP::r[s];
     template <int s> static constexpr int Q = P / RP::r[s];
     template <int s> static constexpr int BF = B * (P / RP::r[s]);
-    template <int s> static constexpr int NB = (BF<s> + NT - 1) / NT;
-    template <int s> static constexpr bool FULL = (BF<s> % NT) == 0;
+    // Slots: a thread holds NB slots of RS elements per stage.  A slot is a
+    // whole butterfly on the vector ALUs, or half of one (8 of 16 elements)
+    // on a matrix-core stage, where a wavefront spans 32 butterflies.
+    template <int s> static constexpr bool MF = (MT > 0) && (RP::r[s] == 16);
+    template <int s> static constexpr int RS = MF<s> ? 8 : RP::r[s];
+    template <int s> static constexpr int NTV = MF<s> ? NT / 2 : NT;
+    template <int s> static constexpr int WVW = MF<s> ? 32 : 64;
+    template <int s> static constexpr int NB = (BF<s> + NTV<s> - 1) / NTV<s>;
+    template <int s> static constexpr bool FULL = (BF<s> % NTV<s>) == 0;
 
-    template <int s> using Regs = RegBlock<V, NB<s>, R<s>>;
+    template <int s> using Regs = RegBlock<V, NB<s>, RS<s>>;
 
     __device__ __forceinline__ static int lidx(int p, int k) { return p * LP + k + (k >> 4); }
+
+    // virtual thread index and element offset of this thread for stage s
+    template <int s> __device__ __forceinline__ static int vthread()
+    {
+        const int tid = threadIdx.x;
+        if constexpr (MF<s>) return (tid >> 6) * 32 + (tid & 31);
+        else return tid;
+    }
+    template <int s> __device__ __forceinline__ static int roff()
+    {
+        if constexpr (MF<s>) return 8 * ((threadIdx.x & 63) >> 5);
+        else return 0;
+    }
 
     template <int s, int MAP> __device__ __forceinline__ static void pj(int b, int& p, int& j)
     {
@@ -117,41 +233,44 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine
             j = b % Q<s>;
             p = b / Q<s>;
         } else {
-            const int i = b / NT, t = b % NT;
-            const int wb = (t & 63) + 64 * i;
-            p = (t >> 6) * PPW + wb / Q<s>;
+            const int i = b / NTV<s>, t = b % NTV<s>;
+            const int wb = (t % WVW<s>) + WVW<s> * i;
+            p = (t / WVW<s>) * PPW + wb / Q<s>;
             j = wb % Q<s>;
         }
     }
     template <int s, int MAP> __device__ __forceinline__ static bool valid(int b)
     {
         if constexpr (MAP == MAP_WV) {
-            if constexpr ((PPW * Q<s>) % 64 == 0) return true;
-            else return ((b % NT) & 63) + 64 * (b / NT) < PPW * Q<s>;
+            if constexpr ((PPW * Q<s>) % WVW<s> == 0) return true;
+            else return (b % NTV<s>) % WVW<s> + WVW<s> * (b / NTV<s>) < PPW * Q<s>;
         } else {
             return FULL<s> || b < BF<s>;
         }
     }
 
-    // Stage-s twiddles and DFT on the registers of every butterfly this thread owns.
-    template <int s, int DIR, int MAP> __device__ __forceinline__ static void compute(Regs<s>& g, const V* __restrict__ tw)
+    // Stage-s twiddles and DFT on every slot this thread owns.
+    template <int s, int DIR, int MAP>
+    __device__ __forceinline__ static void compute(Regs<s>& g, const V* __restrict__ tw, const SA& sa)
     {
         constexpr int Rs = R<s>;
         constexpr int NSs = RP::ns(s);
-        const int tid = threadIdx.x;
+        const int vt = vthread<s>(), ro = roff<s>();
 #pragma unroll
         for (int i = 0; i < NB<s>; ++i) {
-            const int b = tid + i * NT;
+            const int b = vt + i * NTV<s>;
             if constexpr (NSs > 1) {
                 int p, j;
                 pj<s, MAP>(b, p, j);
                 if (valid<s, MAP>(b)) {
-                    const V* row = tw + RP::tw_off(s) + (j % NSs) * Rs;
+                    const V* row = tw + RP::tw_off(s) + (j % NSs) * Rs + ro;
 #pragma unroll
-                    for (int r = 1; r < Rs; ++r) g.v[i][r] = ctw<DIR>(g.v[i][r], row[r]);
+                    for (int q = 0; q < RS<s>; ++q)
+                        if (MF<s> || q > 0) g.v[i][q] = ctw<DIR>(g.v[i][q], row[q]);
                 }
             }
-            dft<Rs, DIR>(g.v[i]);
+            if constexpr (MF<s>) dft16_split<MT, DIR>(g.v[i], sa);
+            else dft<Rs, DIR>(g.v[i]);
         }
     }
 
@@ -159,61 +278,85 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine
     {
         constexpr int Rs = R<s>;
         constexpr int NSs = RP::ns(s);
-        const int tid = threadIdx.x;
+        const int vt = vthread<s>(), ro = roff<s>();
 #pragma unroll
         for (int i = 0; i < NB<s>; ++i) {
-            const int b = tid + i * NT;
+            const int b = vt + i * NTV<s>;
             if (!valid<s, MAP>(b)) continue;
             int p, j;
             pj<s, MAP>(b, p, j);
             const int k0 = (j / NSs) * NSs * Rs + (j % NSs);
+            // LDS addresses as one base plus compile-time offsets where the
+            // pad-every-16 layout allows it
+            if constexpr (NSs % 16 == 0) {
+                V* base = lds + lidx(p, k0) + (ro * NSs) * 17 / 16;
 #pragma unroll
-            for (int r = 0; r < Rs; ++r) lds[lidx(p, k0 + r * NSs)] = g.v[i][r];
+                for (int q = 0; q < RS<s>; ++q) base[(q * NSs) * 17 / 16] = g.v[i][q];
+            } else if constexpr (NSs == 1 && Rs % 16 == 0) {
+                V* base = lds + lidx(p, k0) + ro;  // k0 = j R is a multiple of 16, ro + q < 16 or ro = 0
+#pragma unroll
+                for (int q = 0; q < RS<s>; ++q) base[q + (q >> 4)] = g.v[i][q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < RS<s>; ++q) lds[lidx(p, k0 + (ro + q) * NSs)] = g.v[i][q];
+            }
         }
     }
 
     template <int s, int MAP> __device__ __forceinline__ static void load_lds(Regs<s>& g, const V* lds)
     {
-        constexpr int Rs = R<s>;
-        const int tid = threadIdx.x;
+        const int vt = vthread<s>(), ro = roff<s>();
 #pragma unroll
         for (int i = 0; i < NB<s>; ++i) {
-            const int b = tid + i * NT;
+            const int b = vt + i * NTV<s>;
             if (!valid<s, MAP>(b)) {
 #pragma unroll
-                for (int r = 0; r < Rs; ++r) g.v[i][r] = V{T(0), T(0)};
+                for (int q = 0; q < RS<s>; ++q) g.v[i][q] = V{T(0), T(0)};
                 continue;
             }
             int p, j;
             pj<s, MAP>(b, p, j);
+            if constexpr (Q<s> % 16 == 0) {
+                const V* base = lds + lidx(p, j) + (ro * Q<s>) * 17 / 16;
 #pragma unroll
-            for (int r = 0; r < Rs; ++r) g.v[i][r] = lds[lidx(p, j + r * Q<s>)];
+                for (int q = 0; q < RS<s>; ++q) g.v[i][q] = base[(q * Q<s>) * 17 / 16];
+            } else {
+#pragma unroll
+                for (int q = 0; q < RS<s>; ++q) g.v[i][q] = lds[lidx(p, j + (ro + q) * Q<s>)];
+            }
         }
     }
 
     // Stage-0 inputs from ld(p, idx); idx >= LIN reads as zero.
     template <int MAP, int LIN, class LD> __device__ __forceinline__ static void load_first(Regs<0>& g, LD& ld)
     {
-        constexpr int Rs = R<0>;
         constexpr int Qs = Q<0>;
-        const int tid = threadIdx.x;
+        const int vt = vthread<0>(), ro = roff<0>();
 #pragma unroll
         for (int i = 0; i < NB<0>; ++i) {
-            const int b = tid + i * NT;
+            const int b = vt + i * NTV<0>;
             int p, j;
             pj<0, MAP>(b, p, j);
             const bool ok = valid<0, MAP>(b);
-            static_for<0, Rs>([&](auto rc) {
-                constexpr int r = decltype(rc)::value;
-                const int idx = j + r * Qs;
-                if constexpr ((r + 1) * Qs <= LIN) {
-                    g.v[i][r] = ok ? ld(p, idx) : V{T(0), T(0)};
-                } else if constexpr (r * Qs >= LIN) {
-                    g.v[i][r] = V{T(0), T(0)};
-                } else {
-                    g.v[i][r] = (ok && idx < LIN) ? ld(p, idx) : V{T(0), T(0)};
+            if constexpr (MF<0>) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int idx = j + (ro + q) * Qs;
+                    g.v[i][q] = (ok && idx < LIN) ? ld(p, idx) : V{T(0), T(0)};
                 }
-            });
+            } else {
+                static_for<0, RS<0>>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    const int idx = j + r * Qs;
+                    if constexpr ((r + 1) * Qs <= LIN) {
+                        g.v[i][r] = ok ? ld(p, idx) : V{T(0), T(0)};
+                    } else if constexpr (r * Qs >= LIN) {
+                        g.v[i][r] = V{T(0), T(0)};
+                    } else {
+                        g.v[i][r] = (ok && idx < LIN) ? ld(p, idx) : V{T(0), T(0)};
+                    }
+                });
+            }
         }
     }
 
@@ -221,39 +364,63 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine
     template <int MAP, int LOUT, class ST> __device__ __forceinline__ static void store_last(const Regs<S - 1>& g, ST& st)
     {
         constexpr int s = S - 1;
-        constexpr int Rs = R<s>;
         constexpr int Qs = Q<s>;
-        const int tid = threadIdx.x;
+        const int vt = vthread<s>(), ro = roff<s>();
 #pragma unroll
         for (int i = 0; i < NB<s>; ++i) {
-            const int b = tid + i * NT;
+            const int b = vt + i * NTV<s>;
             if (!valid<s, MAP>(b)) continue;
             int p, j;
             pj<s, MAP>(b, p, j);
-            static_for<0, Rs>([&](auto rc) {
-                constexpr int r = decltype(rc)::value;
-                const int idx = j + r * Qs;
-                if constexpr ((r + 1) * Qs <= LOUT) {
-                    st(p, idx, g.v[i][r]);
-                } else if constexpr (r * Qs >= LOUT) {
-                } else {
-                    if (idx < LOUT) st(p, idx, g.v[i][r]);
+            if constexpr (MF<s>) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int idx = j + (ro + q) * Qs;
+                    if (idx < LOUT) st(p, idx, g.v[i][q]);
                 }
-            });
+            } else {
+                static_for<0, RS<s>>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    const int idx = j + r * Qs;
+                    if constexpr ((r + 1) * Qs <= LOUT) {
+                        st(p, idx, g.v[i][r]);
+                    } else if constexpr (r * Qs >= LOUT) {
+                    } else {
+                        if (idx < LOUT) st(p, idx, g.v[i][r]);
+                    }
+                });
+            }
+        }
+    }
+
+    // f(p, idx, v&) on every element held after stage s (index in natural
+    // order of that stage's outputs when s is the last stage).
+    template <int s, int MAP, class F> __device__ __forceinline__ static void for_each_out(Regs<s>& g, F& f)
+    {
+        const int vt = vthread<s>(), ro = roff<s>();
+#pragma unroll
+        for (int i = 0; i < NB<s>; ++i) {
+            const int b = vt + i * NTV<s>;
+            if (!valid<s, MAP>(b)) continue;
+            int p, j;
+            pj<s, MAP>(b, p, j);
+#pragma unroll
+            for (int q = 0; q < RS<s>; ++q) f(p, j + (ro + q) * Q<s>, g.v[i][q]);
         }
     }
 
     // Middle stages [S0, S1) through LDS with mapping MAP.
-    template <int s, int S1, int DIR, int MAP> __device__ __forceinline__ static void middle(V* lds, const V* tw)
+    template <int s, int S1, int DIR, int MAP>
+    __device__ __forceinline__ static void middle(V* lds, const V* tw, const SA& sa)
     {
         if constexpr (s < S1) {
             Regs<s> g;
             sync();
             load_lds<s, MAP>(g, lds);
-            compute<s, DIR, MAP>(g, tw);
+            compute<s, DIR, MAP>(g, tw, sa);
             sync();
             store_lds<s, MAP>(g, lds);
-            middle<s + 1, S1, DIR, MAP>(lds, tw);
+            middle<s + 1, S1, DIR, MAP>(lds, tw, sa);
         }
     }
 
@@ -261,12 +428,12 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine
     // into the same LDS buffer, so a barrier separates the last reads from
     // those writes.
     template <int DIR, int MAP_IN, int MAP_MID, int MAP_OUT, int LIN, int LOUT, bool DST_LDS = false, class LD, class ST>
-    __device__ __forceinline__ static void run(V* lds, const V* __restrict__ tw, LD& ld, ST& st)
+    __device__ __forceinline__ static void run(V* lds, const V* __restrict__ tw, LD& ld, ST& st, const SA& sa = SA{})
     {
         if constexpr (S == 1) {
             Regs<0> g;
             load_first<MAP_IN, LIN>(g, ld);
-            compute<0, DIR, MAP_IN>(g, tw);
+            compute<0, DIR, MAP_IN>(g, tw, sa);
             if constexpr (MAP_IN == MAP_OUT) {
                 if constexpr (DST_LDS) sync();
                 store_last<MAP_OUT, LOUT>(g, st);
@@ -293,16 +460,16 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine
             {
                 Regs<0> g;
                 load_first<MAP_IN, LIN>(g, ld);
-                compute<0, DIR, MAP_IN>(g, tw);
+                compute<0, DIR, MAP_IN>(g, tw, sa);
                 sync();
                 store_lds<0, MAP_IN>(g, lds);
             }
-            middle<1, S - 1, DIR, MAP_MID>(lds, tw);
+            middle<1, S - 1, DIR, MAP_MID>(lds, tw, sa);
             {
                 Regs<S - 1> g;
                 sync();
                 load_lds<S - 1, MAP_OUT>(g, lds);
-                compute<S - 1, DIR, MAP_OUT>(g, tw);
+                compute<S - 1, DIR, MAP_OUT>(g, tw, sa);
                 if constexpr (DST_LDS) sync();
                 store_last<MAP_OUT, LOUT>(g, st);
             }
@@ -312,46 +479,48 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false> struct Engine
     // Forward stages ending in registers: the last stage's outputs for each
     // owned butterfly (p, j) sit in g.v[i][r] at natural index j + r P/R.
     template <int DIR, int MAP_IN, int MAP_MID, int MAP_OUT, int LIN, class LD>
-    __device__ __forceinline__ static void run_to_regs(V* lds, const V* __restrict__ tw, LD& ld, Regs<S - 1>& out)
+    __device__ __forceinline__ static void run_to_regs(V* lds, const V* __restrict__ tw, LD& ld, Regs<S - 1>& out,
+                                                       const SA& sa = SA{})
     {
         if constexpr (S == 1) {
             static_assert(MAP_IN == MAP_OUT, "single-stage plans need one mapping");
             load_first<MAP_IN, LIN>(out, ld);
-            compute<0, DIR, MAP_IN>(out, tw);
+            compute<0, DIR, MAP_IN>(out, tw, sa);
         } else {
             {
                 Regs<0> g;
                 load_first<MAP_IN, LIN>(g, ld);
-                compute<0, DIR, MAP_IN>(g, tw);
+                compute<0, DIR, MAP_IN>(g, tw, sa);
                 sync();
                 store_lds<0, MAP_IN>(g, lds);
             }
-            middle<1, S - 1, DIR, MAP_MID>(lds, tw);
+            middle<1, S - 1, DIR, MAP_MID>(lds, tw, sa);
             sync();
             load_lds<S - 1, MAP_OUT>(out, lds);
-            compute<S - 1, DIR, MAP_OUT>(out, tw);
+            compute<S - 1, DIR, MAP_OUT>(out, tw, sa);
         }
     }
 
     // Stages starting from registers that already hold the stage-0 inputs
     // (index j + r P/R for each owned butterfly (p, j) under MAP_IN).
     template <int DIR, int MAP_IN, int MAP_MID, int MAP_OUT, int LOUT, class ST>
-    __device__ __forceinline__ static void run_from_regs(V* lds, const V* __restrict__ tw, Regs<0>& g, ST& st)
+    __device__ __forceinline__ static void run_from_regs(V* lds, const V* __restrict__ tw, Regs<0>& g, ST& st,
+                                                         const SA& sa = SA{})
     {
         if constexpr (S == 1) {
             static_assert(MAP_IN == MAP_OUT, "single-stage plans need one mapping");
-            compute<0, DIR, MAP_IN>(g, tw);
+            compute<0, DIR, MAP_IN>(g, tw, sa);
             store_last<MAP_OUT, LOUT>(g, st);
         } else {
-            compute<0, DIR, MAP_IN>(g, tw);
+            compute<0, DIR, MAP_IN>(g, tw, sa);
             sync();
             store_lds<0, MAP_IN>(g, lds);
-            middle<1, S - 1, DIR, MAP_MID>(lds, tw);
+            middle<1, S - 1, DIR, MAP_MID>(lds, tw, sa);
             {
                 Regs<S - 1> h;
                 sync();
                 load_lds<S - 1, MAP_OUT>(h, lds);
-                compute<S - 1, DIR, MAP_OUT>(h, tw);
+                compute<S - 1, DIR, MAP_OUT>(h, tw, sa);
                 store_last<MAP_OUT, LOUT>(h, st);
             }
         }

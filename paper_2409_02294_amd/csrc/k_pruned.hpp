@@ -32,34 +32,37 @@ namespace ps {
 // their shared Ghat row once.
 __device__ __forceinline__ int z_pencil_ky(int q, int N)
 {
-    if (q < 2) return q == 0 ? 0 : N;
     const int i = q >> 1;
-    return (q & 1) ? 2 * N - i : i;
+    const int odd = i == 0 ? N : 2 * N - i;
+    return (q & 1) ? odd : i;
 }
 
 // ---------------------------------------------------------------------------
 // x_r2c: 16 rows (8 packed pairs) of one z-plane per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ rho, cx<T>* __restrict__ t1,
-                                              const cx<T>* __restrict__ tw)
+                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, 8, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, 8, NT, false, MT>;
+    typename E::SA sa;
+    sa.load(stab);
     constexpr int N = P / 2, H = N + 1;
     __shared__ V lds[E::LDS_ELEMS];
     const int y0 = blockIdx.x * 16;
     const int z = blockIdx.y;
-    const T* plane = rho + (size_t)z * N * N;
+    const T* plane = rho + ((size_t)z * N + y0) * N;  // block-uniform base, 32-bit offsets below
     auto ld = [&](int p, int idx) -> V {
         const int ya = y0 + 2 * p;
-        const T a = ya < N ? plane[(size_t)ya * N + idx] : T(0);
-        const T b = ya + 1 < N ? plane[(size_t)(ya + 1) * N + idx] : T(0);
+        const T a = ya < N ? plane[(unsigned)(2 * p * N + idx)] : T(0);
+        const T b = ya + 1 < N ? plane[(unsigned)((2 * p + 1) * N + idx)] : T(0);
         return V{a, b};
     };
     auto st = [&](int p, int idx, V v) { lds[E::lidx(p, idx)] = v; };
-    E::template run<-1, MAP_EF, MAP_MID, MAP_EF, N, P, true>(lds, tw, ld, st);
+    E::template run<-1, MAP_EF, MAP_MID, MAP_EF, N, P, true>(lds, tw, ld, st, sa);
     __syncthreads();
+    V* t1z = t1 + (size_t)z * N;
     for (int e = threadIdx.x; e < 16 * H; e += NT) {
         const int row = e & 15, k = e >> 4;
         const int y = y0 + row;
@@ -73,32 +76,34 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ rho, cx<T>* 
         } else {
             x = V{T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
         }
-        t1[((size_t)k * N + z) * N + y] = x;
+        t1z[(unsigned)(k * N * N + y)] = x;
     }
 }
 
 // ---------------------------------------------------------------------------
 // y_fwd: ZT z-pencils of one kx per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* __restrict__ t1, cx<T>* __restrict__ t2,
-                                              const cx<T>* __restrict__ tw)
+                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ZT, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ZT, NT, false, MT>;
+    typename E::SA sa;
+    sa.load(stab);
     constexpr int N = P / 2;
     __shared__ V lds[E::LDS_ELEMS];
     const int z0 = blockIdx.x * ZT;
     const int kx = blockIdx.y;
-    const V* in = t1 + (size_t)kx * N * N;
-    V* out = t2 + (size_t)kx * P * N;
+    const V* in = t1 + ((size_t)kx * N + z0) * N;
+    V* out = t2 + (size_t)kx * P * N + z0;
     auto ld = [&](int p, int idx) -> V {
-        return z0 + p < N ? in[(size_t)(z0 + p) * N + idx] : V{T(0), T(0)};
+        return z0 + p < N ? in[(unsigned)(p * N + idx)] : V{T(0), T(0)};
     };
     auto st = [&](int p, int idx, V v) {
-        if (z0 + p < N) out[(size_t)idx * N + z0 + p] = v;
+        if (z0 + p < N) out[(unsigned)(idx * N + p)] = v;
     };
-    E::template run<-1, MAP_EF, MAP_MID, MAP_PF, N, P>(lds, tw, ld, st);
+    E::template run<-1, MAP_EF, MAP_MID, MAP_PF, N, P>(lds, tw, ld, st, sa);
 }
 
 // ---------------------------------------------------------------------------
@@ -106,13 +111,16 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* __restrict__ t1, cx<T
 // WAVE: each wavefront owns its pencils for the whole transform and the stage
 // exchanges synchronise the wavefront only.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int B, int NT, bool WAVE>
+template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT>
 __global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* __restrict__ ghat,
-                                               const cx<T>* __restrict__ twf, const cx<T>* __restrict__ twi)
+                                               const cx<T>* __restrict__ twf, const cx<T>* __restrict__ twi,
+                                               const unsigned short* __restrict__ stab)
 {
     using V = cx<T>;
-    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE>;
-    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE>;
+    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE, MT>;
+    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE, MT>;
+    typename EF::SA sa;
+    sa.load(stab);
     constexpr int MAP_IO = WAVE ? MAP_WV : MAP_EF;
     constexpr int MAP_MID = MAP_IO, MAP_Z = MAP_IO;
     static_assert(EF::LDS_ELEMS == EI::LDS_ELEMS, "plans share one LDS buffer");
@@ -122,78 +130,84 @@ __global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* 
     const int q0 = blockIdx.x * B;
     const int kx = blockIdx.y;
     V* base = t2 + (size_t)kx * P * N;
-    auto ld = [&](int p, int idx) -> V { return base[(size_t)z_pencil_ky(q0 + p, N) * N + idx]; };
+    const T* grow = ghat + (size_t)kx * H * H;
+    // With one pencil per wavefront the pencil index is wavefront-uniform:
+    // keep its row pointers in scalar registers.
+    constexpr bool ONE = WAVE && EF::PPW == 1;
+    const int pw = ONE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+    const int kyw = z_pencil_ky(q0 + pw, N);
+    V* roww = base + (size_t)kyw * N;
+    const T* growm = grow + (size_t)(kyw <= N ? kyw : P - kyw) * H;
+    auto prow = [&](int p) -> V* { return ONE ? roww : base + (unsigned)(z_pencil_ky(q0 + p, N) * N); };
+    auto ld = [&](int p, int idx) -> V { return prow(p)[idx]; };
     typename EF::template Regs<SL> g;
-    EF::template run_to_regs<-1, MAP_IO, MAP_MID, MAP_Z, N>(lds, twf, ld, g);
+    EF::template run_to_regs<-1, MAP_IO, MAP_MID, MAP_Z, N>(lds, twf, ld, g, sa);
     // multiply by the real, even transformed kernel at (kz, ky, kx)
-    {
-        constexpr int R = EF::template R<SL>;
-        constexpr int Q = P / R;
-        const T* grow = ghat + (size_t)kx * H * H;
-#pragma unroll
-        for (int i = 0; i < EF::template NB<SL>; ++i) {
-            const int b = threadIdx.x + i * NT;
-            if (!EF::template valid<SL, MAP_Z>(b)) continue;
-            int p, j;
-            EF::template pj<SL, MAP_Z>(b, p, j);
+    auto mul = [&](int p, int kz, V& v) {
+        const T* gr;
+        if constexpr (ONE) {
+            gr = growm;
+        } else {
             const int ky = z_pencil_ky(q0 + p, N);
-            const int kyf = ky <= N ? ky : P - ky;
-            const T* gr = grow + (size_t)kyf * H;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int kz = j + r * Q;
-                const T gv = gr[kz <= N ? kz : P - kz];
-                g.v[i][r] = V{g.v[i][r].x * gv, g.v[i][r].y * gv};
-            }
+            gr = grow + (unsigned)((ky <= N ? ky : P - ky) * H);
         }
-    }
-    auto st = [&](int p, int idx, V v) { base[(size_t)z_pencil_ky(q0 + p, N) * N + idx] = v; };
-    EI::template run_from_regs<+1, MAP_Z, MAP_MID, MAP_IO, N>(lds, twi, g, st);
+        const int kf = kz <= N ? kz : P - kz;
+        const T gv = gr[kf];
+        v = V{v.x * gv, v.y * gv};
+    };
+    EF::template for_each_out<SL, MAP_Z>(g, mul);
+    auto st = [&](int p, int idx, V v) { prow(p)[idx] = v; };
+    EI::template run_from_regs<+1, MAP_Z, MAP_MID, MAP_IO, N>(lds, twi, g, st, sa);
 }
 
 // ---------------------------------------------------------------------------
 // y_inv: ZT z-pencils of one kx per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* __restrict__ t2, cx<T>* __restrict__ t1,
-                                              const cx<T>* __restrict__ tw)
+                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT, false, MT>;
+    typename E::SA sa;
+    sa.load(stab);
     constexpr int N = P / 2;
     __shared__ V lds[E::LDS_ELEMS];
     const int z0 = blockIdx.x * ZT;
     const int kx = blockIdx.y;
-    const V* in = t2 + (size_t)kx * P * N;
-    V* out = t1 + (size_t)kx * N * N;
+    const V* in = t2 + (size_t)kx * P * N + z0;
+    V* out = t1 + ((size_t)kx * N + z0) * N;
     auto ld = [&](int p, int idx) -> V {
-        return z0 + p < N ? in[(size_t)idx * N + z0 + p] : V{T(0), T(0)};
+        return z0 + p < N ? in[(unsigned)(idx * N + p)] : V{T(0), T(0)};
     };
     auto st = [&](int p, int idx, V v) {
-        if (z0 + p < N) out[(size_t)(z0 + p) * N + idx] = v;
+        if (z0 + p < N) out[(unsigned)(p * N + idx)] = v;
     };
-    E::template run<+1, MAP_PF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st);
+    E::template run<+1, MAP_PF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
 }
 
 // ---------------------------------------------------------------------------
 // x_c2r: 16 rows (8 packed pairs) of one z-plane per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int NT, int MAP_MID>
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ t1, T* __restrict__ phi,
-                                              const cx<T>* __restrict__ tw)
+                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT, false, MT>;
+    typename E::SA sa;
+    sa.load(stab);
     constexpr int N = P / 2, H = N + 1;
     constexpr int XP = H + 1;  // pitch of the staged half spectra
     constexpr int LDS = E::LDS_ELEMS > 16 * XP ? E::LDS_ELEMS : 16 * XP;
     __shared__ V lds[LDS];
     const int y0 = blockIdx.x * 16;
     const int z = blockIdx.y;
+    const V* t1z = t1 + (size_t)z * N + y0;
     for (int e = threadIdx.x; e < 16 * H; e += NT) {
         const int row = e & 15, k = e >> 4;
         const int y = y0 + row;
-        lds[row * XP + k] = y < N ? t1[((size_t)k * N + z) * N + y] : V{T(0), T(0)};
+        lds[row * XP + k] = y < N ? t1z[(unsigned)(k * N * N + row)] : V{T(0), T(0)};
     }
     __syncthreads();
     auto ld = [&](int p, int idx) -> V {
@@ -213,13 +227,13 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ t1, T* _
         }
         return V{a.x - b.y, a.y + b.x};
     };
-    T* plane = phi + (size_t)z * N * N;
+    T* plane = phi + ((size_t)z * N + y0) * N;
     auto st = [&](int p, int idx, V v) {
         const int ya = y0 + 2 * p;
-        if (ya < N) plane[(size_t)ya * N + idx] = v.x;
-        if (ya + 1 < N) plane[(size_t)(ya + 1) * N + idx] = v.y;
+        if (ya < N) plane[(unsigned)(2 * p * N + idx)] = v.x;
+        if (ya + 1 < N) plane[(unsigned)((2 * p + 1) * N + idx)] = v.y;
     };
-    E::template run<+1, MAP_EF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st);
+    E::template run<+1, MAP_EF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
 }
 
 }  // namespace ps

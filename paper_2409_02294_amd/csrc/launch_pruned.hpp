@@ -1,5 +1,6 @@
-// Launchers of the pruned pipeline for float and double, every supported P,
-// with the per-plan kernel variant.
+// Launchers of the pruned pipeline for every supported P, with the per-plan
+// kernel variant; instantiated per arithmetic by the launch_pruned_*.hip units.
+#pragma once
 #include "k_pruned.hpp"
 #include "ps_internal.hpp"
 
@@ -20,7 +21,7 @@ constexpr int wave_threads(int B, int P, int E)
     return 64 * (B / ppw);
 }
 
-template <typename T, int P, int FAM> struct PassLaunch {
+template <typename T, int P, int FAM, int MT> struct PassLaunch {
     using V = cx<T>;
     static constexpr int N = P / 2, H = N + 1;
     static constexpr int ZT = PrunedShape<T>::ZT, ZB = PrunedShape<T>::ZB;
@@ -30,38 +31,39 @@ template <typename T, int P, int FAM> struct PassLaunch {
 
     static void x_r2c(const PrunedBufs& b, const V* tw)
     {
-        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTX, MAP_EF>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
-                           static_cast<const T*>(b.rho), static_cast<V*>(b.t1), tw);
+        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
+                           static_cast<const T*>(b.rho), static_cast<V*>(b.t1), tw, b.stab);
     }
     static void y_fwd(const PrunedBufs& b, const V* tw)
     {
-        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0, b.stream,
-                           static_cast<const V*>(b.t1), static_cast<V*>(b.t2), tw);
+        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0,
+                           b.stream, static_cast<const V*>(b.t1), static_cast<V*>(b.t2), tw, b.stab);
     }
     template <bool WAVE> static void z_conv(const PrunedBufs& b, const V* twf, const V* twi)
     {
         constexpr int NTZ = WAVE ? wave_threads(ZB, P, E) : threads_for(ZB, P, E);
-        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE>), dim3(P / ZB, H), dim3(NTZ), 0, b.stream,
-                           static_cast<V*>(b.t2), static_cast<const T*>(b.ghat), twf, twi);
+        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H), dim3(NTZ), 0, b.stream,
+                           static_cast<V*>(b.t2), static_cast<const T*>(b.ghat), twf, twi, b.stab);
     }
     static void y_inv(const PrunedBufs& b, const V* tw)
     {
-        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0, b.stream,
-                           static_cast<const V*>(b.t2), static_cast<V*>(b.t1), tw);
+        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0,
+                           b.stream, static_cast<const V*>(b.t2), static_cast<V*>(b.t1), tw, b.stab);
     }
     static void x_c2r(const PrunedBufs& b, const V* tw)
     {
-        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
-                           static_cast<const V*>(b.t1), static_cast<T*>(b.phi), tw);
+        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
+                           static_cast<const V*>(b.t1), static_cast<T*>(b.phi), tw, b.stab);
     }
 };
 
-template <typename T, int P> static hipError_t pruned_passes(int lo, int hi, const PrunedBufs& b)
+// Split matrix-core plans keep the radix-16 family (family 1 has no radix-16 stage).
+template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int hi, const PrunedBufs& b)
 {
     using V = cx<T>;
-    using L0 = PassLaunch<T, P, 0>;
-    constexpr bool F1 = has_fam1<P>();
-    using L1 = PassLaunch<T, P, F1 ? 1 : 0>;
+    using L0 = PassLaunch<T, P, 0, MT>;
+    constexpr bool F1 = has_fam1<P>() && MT == 0;
+    using L1 = PassLaunch<T, P, F1 ? 1 : 0, MT>;
     const V* twf0 = static_cast<const V*>(b.twf);
     const V* twi0 = static_cast<const V*>(b.twi);
     const V* twf1 = static_cast<const V*>(F1 ? b.twf1 : b.twf);
@@ -99,19 +101,16 @@ template <typename T, int P> static hipError_t pruned_passes(int lo, int hi, con
     return hipSuccess;
 }
 
-template <typename T> static hipError_t pruned_dispatch(int P, int lo, int hi, const PrunedBufs& b)
+template <typename T, int MT> static hipError_t pruned_dispatch(int P, int lo, int hi, const PrunedBufs& b)
 {
     switch (P) {
 #define PS_CASE(PP) \
-    case PP: return pruned_passes<T, PP>(lo, hi, b);
+    case PP: return pruned_passes<T, PP, MT>(lo, hi, b);
         PS_CASE(16) PS_CASE(32) PS_CASE(48) PS_CASE(64) PS_CASE(96) PS_CASE(128)
         PS_CASE(192) PS_CASE(256) PS_CASE(384) PS_CASE(512) PS_CASE(768) PS_CASE(1024)
 #undef PS_CASE
     default: return hipErrorInvalidValue;
     }
 }
-
-hipError_t pruned_run_f32(int P, int lo, int hi, const PrunedBufs& b) { return pruned_dispatch<float>(P, lo, hi, b); }
-hipError_t pruned_run_f64(int P, int lo, int hi, const PrunedBufs& b) { return pruned_dispatch<double>(P, lo, hi, b); }
 
 }  // namespace ps

@@ -88,6 +88,60 @@ std::vector<std::complex<double>> plan_table(const std::vector<int>& rad)
     return t;
 }
 
+// Round a double to the nearest bf16 value (8 significant bits, ties to even).
+double bf16_round(double a)
+{
+    if (a == 0.0 || !std::isfinite(a)) return a;
+    int e;
+    const double m = std::frexp(a, &e);  // a = m 2^e, 0.5 <= |m| < 1
+    return std::ldexp(std::nearbyint(std::ldexp(m, 8)), e - 8);
+}
+
+unsigned short bf16_bits(double v)  // v already a bf16 value
+{
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (unsigned short)(u >> 16);
+}
+
+// Matrix pieces of the split-bf16 DFT-16 in the lane layout of
+// v_mfma_f32_32x32x16_bf16's A operand: [piece][K chunk][lane][8].  Row m of
+// the operand is row perm(m) of the real 32x32 forward DFT-16 matrix
+// [[Wr, -Wi], [Wi, Wr]], perm(8j + 4h + i) = 16 (j / 2) + 8 h + 4 (j % 2) + i,
+// so that a lane's accumulator holds the outputs whose inputs it held.
+std::vector<unsigned short> split_dft16_table()
+{
+    double M[32][32];
+    for (int a = 0; a < 16; ++a)
+        for (int b = 0; b < 16; ++b) {
+            double c, sn;
+            unit_root((long)a * b, 16, c, sn);
+            const double wr = c, wi = -sn;  // exp(-2 pi i ab / 16)
+            M[a][b] = wr;
+            M[a][16 + b] = -wi;
+            M[16 + a][b] = wi;
+            M[16 + a][16 + b] = wr;
+        }
+    std::vector<unsigned short> t(3 * 2 * 64 * 8);
+    for (int chunk = 0; chunk < 2; ++chunk)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int i = 0; i < 8; ++i) {
+                const int m = lane % 32, kk = 8 * (lane / 32) + i;
+                const int j = m / 8, hh = (m / 4) % 2, ii = m % 4;
+                const int row = 16 * (j / 2) + 8 * hh + 4 * (j % 2) + ii;
+                const double v = M[row][16 * chunk + kk];
+                const double p0 = bf16_round(v);
+                const double r1 = v - p0;
+                const double p1 = bf16_round(r1);
+                const double p2 = bf16_round(r1 - p1);
+                const double pc[3] = {p0, p1, p2};
+                for (int piece = 0; piece < 3; ++piece)
+                    t[((piece * 2 + chunk) * 64 + lane) * 8 + i] = bf16_bits(pc[piece]);
+            }
+    return t;
+}
+
 template <typename T> void append_table(std::vector<unsigned char>& blob, size_t& off,
                                         const std::vector<std::complex<double>>& t)
 {
@@ -135,6 +189,7 @@ struct ps_plan_s {
     size_t off_tab = 0, tab_bytes = 0;
     size_t tw_f = 0, tw_i = 0, tw_f64 = 0;  // offsets inside the table blob
     size_t tw_f1 = 0, tw_i1 = 0;            // family-1 plan tables
+    size_t split_tab = 0;                   // split-bf16 DFT-16 matrix pieces
     ps::PrunedVariant var;                  // kernel variant per pass
     size_t off_ghat = 0, ghat_bytes = 0;
     size_t off_t1 = 0, off_t2 = 0;          // pruned intermediates
@@ -167,6 +222,7 @@ ps::PrunedBufs pruned_bufs(ps_plan p, const void* rho, void* phi, hipStream_t s)
     b.twi = p->ws + p->off_tab + p->tw_i;
     b.twf1 = p->ws + p->off_tab + p->tw_f1;
     b.twi1 = p->ws + p->off_tab + p->tw_i1;
+    b.stab = reinterpret_cast<const unsigned short*>(p->ws + p->off_tab + p->split_tab);
     b.var = p->var;
     b.stream = s;
     return b;
@@ -185,6 +241,15 @@ const char* prec_name(ps_precision p)
 }
 
 int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : 2; }
+
+// Runs passes [lo, hi) of a pruned plan's pipeline with its arithmetic.
+hipError_t run_pruned(ps_precision prec, int P, int lo, int hi, const ps::PrunedBufs& b)
+{
+    if (prec == PS_F64) return ps::pruned_run_f64(P, lo, hi, b);
+    if (prec == PS_F32_SPLIT) return b.var.mterms == 3 ? ps::pruned_run_split3(P, lo, hi, b)
+                                                       : ps::pruned_run_split6(P, lo, hi, b);
+    return ps::pruned_run_f32(P, lo, hi, b);
+}
 
 int* variant_slot(ps::PrunedVariant& v, int pass)
 {
@@ -270,8 +335,6 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     if (!supported_n(n))
         return fail(PS_ERR_UNSUPPORTED, "n = " + std::to_string(n) +
                                             " unsupported (2n must be 2^a or 3*2^a with 16 <= 2n <= 1024)");
-    if (prec == PS_F32_SPLIT)
-        return fail(PS_ERR_UNSUPPORTED, "precision " + std::to_string((int)prec) + " is not built into this library");
     ps_plan p = new (std::nothrow) ps_plan_s();
     if (!p) return fail(PS_ERR_INVALID, "out of host memory");
     p->n = n;
@@ -303,8 +366,18 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
         append_table<float>(p->tables, p->tw_i1, ti1);
         append_table<double>(p->tables, p->tw_f64, tf);
     }
-    // default variants: wave-owned z pass; family 1 where it exists
-    if (ps::has_family1(p->P)) {
+    if (prec == PS_F32_SPLIT) {
+        const auto st = split_dft16_table();
+        p->split_tab = align_up(p->tables.size());
+        p->tables.resize(p->split_tab + st.size() * sizeof(unsigned short), 0);
+        std::memcpy(p->tables.data() + p->split_tab, st.data(), st.size() * sizeof(unsigned short));
+    }
+    // default variants: wave-owned z pass; family 1 where it exists (not for
+    // split plans, whose matrix-core stages are the radix-16 ones)
+    if (prec == PS_F32_SPLIT) {
+        p->var.zmode = 1;
+        p->var.mterms = 6;
+    } else if (ps::has_family1(p->P)) {
         p->var.x_fam = p->var.y_fam = p->var.yi_fam = p->var.xc_fam = 1;
         p->var.zmode = 2;
     } else {
@@ -367,6 +440,7 @@ ps_status ps_plan_query(ps_plan p, ps_plan_info* info)
         info->t1_offset = p->off_t1;
         info->t2_offset = p->off_t2;
         for (int k = 0; k < 5; ++k) info->variant[k] = *variant_slot(p->var, k);
+        info->split_terms = p->var.mterms;
     }
     return PS_OK;
 }
@@ -434,7 +508,7 @@ ps_status ps_solve(ps_plan p, const void* d_rho, void* d_phi, void* stream)
         e = is_f64(p->prec) ? ps::plain_run_f64(p->P, b) : ps::plain_run_f32(p->P, b);
     } else {
         const ps::PrunedBufs b = pruned_bufs(p, d_rho, d_phi, st);
-        e = is_f64(p->prec) ? ps::pruned_run_f64(p->P, 0, 5, b) : ps::pruned_run_f32(p->P, 0, 5, b);
+        e = run_pruned(p->prec, p->P, 0, 5, b);
     }
     if (e != hipSuccess) return device_fail(e, "solve launch");
     return PS_OK;
@@ -466,8 +540,7 @@ ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void
     case 3: b.t2 = in; b.t1 = d_out; break;
     case 4: b.t1 = in; b.phi = d_out; break;
     }
-    hipError_t e = is_f64(p->prec) ? ps::pruned_run_f64(p->P, pass, pass + 1, b)
-                                   : ps::pruned_run_f32(p->P, pass, pass + 1, b);
+    hipError_t e = run_pruned(p->prec, p->P, pass, pass + 1, b);
     if (e != hipSuccess) return device_fail(e, "pass launch");
     return PS_OK;
 }
@@ -476,11 +549,17 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
 {
     if (ps_status s = check_plan(p)) return s;
     if (is_plain(p->prec)) return fail(PS_ERR_UNSUPPORTED, "plain plans have no variants");
-    if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..4");
+    if (pass == 5) {
+        if (p->prec != PS_F32_SPLIT) return fail(PS_ERR_UNSUPPORTED, "product terms apply to PS_F32_SPLIT plans");
+        if (variant != 3 && variant != 6) return fail(PS_ERR_INVALID, "split product terms must be 3 or 6");
+        p->var.mterms = variant;
+        return PS_OK;
+    }
+    if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..5");
     if (variant < 0 || variant >= num_variants(pass)) return fail(PS_ERR_INVALID, "variant out of range");
     const bool needs_f1 = (pass == 2) ? variant == 2 : variant == 1;
-    if (needs_f1 && !ps::has_family1(p->P))
-        return fail(PS_ERR_UNSUPPORTED, "this length has no radix-32 plan family");
+    if (needs_f1 && (!ps::has_family1(p->P) || p->prec == PS_F32_SPLIT))
+        return fail(PS_ERR_UNSUPPORTED, "this plan has no radix-32 plan family");
     *variant_slot(p->var, pass) = variant;
     return PS_OK;
 }
@@ -509,14 +588,13 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
         float best_ms = 1e30f;
         for (int v = 0; v < num_variants(pass); ++v) {
             const bool needs_f1 = (pass == 2) ? v == 2 : v == 1;
-            if (needs_f1 && !ps::has_family1(p->P)) continue;
+            if (needs_f1 && (!ps::has_family1(p->P) || p->prec == PS_F32_SPLIT)) continue;
             *variant_slot(b.var, pass) = v;
             const int reps = 5;
             float ms = 0.f;
             for (int r = 0; r <= reps && rc == PS_OK; ++r) {
                 hipEventRecord(e0, st);
-                e = is_f64(p->prec) ? ps::pruned_run_f64(p->P, pass, pass + 1, b)
-                                    : ps::pruned_run_f32(p->P, pass, pass + 1, b);
+                e = run_pruned(p->prec, p->P, pass, pass + 1, b);
                 hipEventRecord(e1, st);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float t = 0.f;

@@ -17,6 +17,7 @@ namespace ps {
 // 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1).
 struct PrunedVariant {
     int x_fam = 0, y_fam = 0, zmode = 0, yi_fam = 0, xc_fam = 0;
+    int mterms = 0;  // 0: vector-ALU DFTs; 3 or 6: split-bf16 matrix-core radix-16 DFTs (float only)
 };
 constexpr int NUM_ZMODES = 3;
 
@@ -32,6 +33,7 @@ struct PrunedBufs {
     const void* twi;   // inverse-plan twiddles, family 0
     const void* twf1;  // forward-plan twiddles, family 1
     const void* twi1;  // inverse-plan twiddles, family 1
+    const unsigned short* stab;  // split-bf16 DFT-16 matrix pieces (mterms > 0)
     PrunedVariant var;
     hipStream_t stream;
 };
@@ -40,6 +42,8 @@ struct PrunedBufs {
 // 3 y_inv, 4 x_c2r).  Returns hipErrorInvalidValue for an unsupported P.
 hipError_t pruned_run_f32(int P, int lo, int hi, const PrunedBufs& b);
 hipError_t pruned_run_f64(int P, int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split6(int P, int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split3(int P, int lo, int hi, const PrunedBufs& b);
 
 // Transformed-kernel build (double precision throughout).
 struct GreenBufs {

@@ -142,7 +142,8 @@ def test_variant_selection_contract():
     q = S.ps_plan_create(256, 1.0 / 256, S.PS_F64)
     try:
         lib = S.load()
-        assert lib.ps_plan_set_variant(p, 5, 0) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 6, 0) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 5, 6) == S.PS_ERR_UNSUPPORTED  # product terms: split plans only
         assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED  # no radix-32 family at P = 64
@@ -171,5 +172,22 @@ def test_tuning_cache_is_read(tmp_path):
     p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32, str(tmp_path / "absent.txt"))
     try:
         assert S.ps_plan_query(p)["variant"] == [1, 1, 2, 1, 1]
+    finally:
+        S.ps_plan_destroy(p)
+
+
+def test_split_plan_contract():
+    p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32_SPLIT)
+    try:
+        info = S.ps_plan_query(p)
+        assert info["split_terms"] == 6
+        assert info["variant"] == [0, 0, 1, 0, 0]
+        lib = S.load()
+        assert lib.ps_plan_set_variant(p, 5, 4) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # keeps the radix-16 family
+        assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
+        S.ps_plan_set_variant(p, 5, 3)
+        assert S.ps_plan_query(p)["split_terms"] == 3
+        assert S.ps_plan_workspace_bytes(p) >= S.ps_plan_workspace_bytes(S.ps_plan_create(256, 1.0 / 256, S.PS_F32))
     finally:
         S.ps_plan_destroy(p)
