@@ -37,203 +37,261 @@ __device__ __forceinline__ int z_pencil_ky(int q, int N)
     return (q & 1) ? odd : i;
 }
 
+// Each pass is a tile function (one workgroup's share, addressed by tile
+// coordinates, using a caller-provided LDS buffer of at least LDS elements),
+// wrapped below as a one-tile-per-workgroup kernel; the persistent batched
+// kernel calls the same tile functions.
+
 // ---------------------------------------------------------------------------
-// x_r2c: 16 rows (8 packed pairs) of one z-plane per workgroup.
+// x_r2c: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
+// ---------------------------------------------------------------------------
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXR2C {
+    using V = cx<T>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, 8, NT, false, MT>;
+    static constexpr int N = P / 2, H = N + 1;
+    static constexpr int LDS = E::LDS_ELEMS;
+    __device__ __forceinline__ static void run(int bx, int by, const T* __restrict__ rho, V* __restrict__ t1,
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+    {
+        const int y0 = bx * 16;
+        const int z = by;
+        const T* plane = rho + ((size_t)z * N + y0) * N;  // block-uniform base, 32-bit offsets below
+        auto ld = [&](int p, int idx) -> V {
+            const int ya = y0 + 2 * p;
+            const T a = ya < N ? plane[(unsigned)(2 * p * N + idx)] : T(0);
+            const T b = ya + 1 < N ? plane[(unsigned)((2 * p + 1) * N + idx)] : T(0);
+            return V{a, b};
+        };
+        auto st = [&](int p, int idx, V v) { lds[E::lidx(p, idx)] = v; };
+        E::template run<-1, MAP_EF, MAP_MID, MAP_EF, N, P, true>(lds, tw, ld, st, sa);
+        __syncthreads();
+        V* t1z = t1 + (size_t)z * N;
+        for (int e = threadIdx.x; e < 16 * H; e += NT) {
+            const int row = e & 15, k = e >> 4;
+            const int y = y0 + row;
+            if (y >= N) continue;
+            const int p = row >> 1;
+            const V z1 = lds[E::lidx(p, k)];
+            const V z2 = lds[E::lidx(p, k == 0 ? 0 : P - k)];
+            V x;
+            if (row & 1) {
+                x = V{T(0.5) * (z1.y + z2.y), T(-0.5) * (z1.x - z2.x)};
+            } else {
+                x = V{T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
+            }
+            t1z[(unsigned)(k * N * N + y)] = x;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// y_fwd: ZT z-pencils of one kx; tile (z-tile bx, kx by).
+// ---------------------------------------------------------------------------
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struct TileYFwd {
+    using V = cx<T>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ZT, NT, false, MT>;
+    static constexpr int N = P / 2;
+    static constexpr int LDS = E::LDS_ELEMS;
+    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t1, V* __restrict__ t2,
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+    {
+        const int z0 = bx * ZT;
+        const int kx = by;
+        const V* in = t1 + ((size_t)kx * N + z0) * N;
+        V* out = t2 + (size_t)kx * P * N + z0;
+        auto ld = [&](int p, int idx) -> V {
+            return z0 + p < N ? in[(unsigned)(p * N + idx)] : V{T(0), T(0)};
+        };
+        auto st = [&](int p, int idx, V v) {
+            if (z0 + p < N) out[(unsigned)(idx * N + p)] = v;
+        };
+        E::template run<-1, MAP_EF, MAP_MID, MAP_PF, N, P>(lds, tw, ld, st, sa);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// z_conv: B z-pencils (ky pencils of one kx), in place; tile (ky-tile bx, kx by).
+// WAVE: each wavefront owns its pencils for the whole transform and the stage
+// exchanges synchronise the wavefront only.
+// ---------------------------------------------------------------------------
+template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT> struct TileZConv {
+    using V = cx<T>;
+    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE, MT>;
+    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE, MT>;
+    static_assert(EF::LDS_ELEMS == EI::LDS_ELEMS, "plans share one LDS buffer");
+    static constexpr int N = P / 2, H = N + 1;
+    static constexpr int LDS = EF::LDS_ELEMS;
+    __device__ __forceinline__ static void run(int bx, int by, V* __restrict__ t2, const T* __restrict__ ghat,
+                                               const V* __restrict__ twf, const V* __restrict__ twi, V* lds,
+                                               const typename EF::SA& sa)
+    {
+        constexpr int MAP_IO = WAVE ? MAP_WV : MAP_EF;
+        constexpr int MAP_MID = MAP_IO, MAP_Z = MAP_IO;
+        constexpr int SL = EF::S - 1;
+        const int q0 = bx * B;
+        const int kx = by;
+        V* base = t2 + (size_t)kx * P * N;
+        const T* grow = ghat + (size_t)kx * H * H;
+        // With one pencil per wavefront the pencil index is wavefront-uniform:
+        // keep its row pointers in scalar registers.
+        constexpr bool ONE = WAVE && EF::PPW == 1;
+        const int pw = ONE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+        const int kyw = z_pencil_ky(q0 + pw, N);
+        V* roww = base + (size_t)kyw * N;
+        const T* growm = grow + (size_t)(kyw <= N ? kyw : P - kyw) * H;
+        auto prow = [&](int p) -> V* { return ONE ? roww : base + (unsigned)(z_pencil_ky(q0 + p, N) * N); };
+        auto ld = [&](int p, int idx) -> V { return prow(p)[idx]; };
+        typename EF::template Regs<SL> g;
+        EF::template run_to_regs<-1, MAP_IO, MAP_MID, MAP_Z, N>(lds, twf, ld, g, sa);
+        // multiply by the real, even transformed kernel at (kz, ky, kx)
+        auto mul = [&](int p, int kz, V& v) {
+            const T* gr;
+            if constexpr (ONE) {
+                gr = growm;
+            } else {
+                const int ky = z_pencil_ky(q0 + p, N);
+                gr = grow + (unsigned)((ky <= N ? ky : P - ky) * H);
+            }
+            const int kf = kz <= N ? kz : P - kz;
+            const T gv = gr[kf];
+            v = V{v.x * gv, v.y * gv};
+        };
+        EF::template for_each_out<SL, MAP_Z>(g, mul);
+        auto st = [&](int p, int idx, V v) { prow(p)[idx] = v; };
+        EI::template run_from_regs<+1, MAP_Z, MAP_MID, MAP_IO, N>(lds, twi, g, st, sa);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// y_inv: ZT z-pencils of one kx; tile (z-tile bx, kx by).
+// ---------------------------------------------------------------------------
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struct TileYInv {
+    using V = cx<T>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT, false, MT>;
+    static constexpr int N = P / 2;
+    static constexpr int LDS = E::LDS_ELEMS;
+    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t2, V* __restrict__ t1,
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+    {
+        const int z0 = bx * ZT;
+        const int kx = by;
+        const V* in = t2 + (size_t)kx * P * N + z0;
+        V* out = t1 + ((size_t)kx * N + z0) * N;
+        auto ld = [&](int p, int idx) -> V {
+            return z0 + p < N ? in[(unsigned)(idx * N + p)] : V{T(0), T(0)};
+        };
+        auto st = [&](int p, int idx, V v) {
+            if (z0 + p < N) out[(unsigned)(p * N + idx)] = v;
+        };
+        E::template run<+1, MAP_PF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// x_c2r: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
+// ---------------------------------------------------------------------------
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXC2R {
+    using V = cx<T>;
+    using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT, false, MT>;
+    static constexpr int N = P / 2, H = N + 1;
+    static constexpr int XP = H + 1;  // pitch of the staged half spectra
+    static constexpr int LDS = E::LDS_ELEMS > 16 * XP ? E::LDS_ELEMS : 16 * XP;
+    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t1, T* __restrict__ phi,
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+    {
+        const int y0 = bx * 16;
+        const int z = by;
+        const V* t1z = t1 + (size_t)z * N + y0;
+        for (int e = threadIdx.x; e < 16 * H; e += NT) {
+            const int row = e & 15, k = e >> 4;
+            const int y = y0 + row;
+            lds[row * XP + k] = y < N ? t1z[(unsigned)(k * N * N + row)] : V{T(0), T(0)};
+        }
+        __syncthreads();
+        auto ld = [&](int p, int idx) -> V {
+            const V* xa = lds + (2 * p) * XP;
+            const V* xb = xa + XP;
+            V a, b;
+            if (idx <= N) {
+                a = xa[idx];
+                b = xb[idx];
+                if (idx == 0 || idx == N) {
+                    a.y = T(0);
+                    b.y = T(0);
+                }
+            } else {
+                a = cconj(xa[P - idx]);
+                b = cconj(xb[P - idx]);
+            }
+            return V{a.x - b.y, a.y + b.x};
+        };
+        T* plane = phi + ((size_t)z * N + y0) * N;
+        auto st = [&](int p, int idx, V v) {
+            const int ya = y0 + 2 * p;
+            if (ya < N) plane[(unsigned)(2 * p * N + idx)] = v.x;
+            if (ya + 1 < N) plane[(unsigned)((2 * p + 1) * N + idx)] = v.y;
+        };
+        E::template run<+1, MAP_EF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One-tile-per-workgroup kernels.
 // ---------------------------------------------------------------------------
 template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ rho, cx<T>* __restrict__ t1,
                                               const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
-    using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, 8, NT, false, MT>;
-    typename E::SA sa;
+    using TL = TileXR2C<T, P, FAM, NT, MAP_MID, MT>;
+    __shared__ cx<T> lds[TL::LDS];
+    typename TL::E::SA sa;
     sa.load(stab);
-    constexpr int N = P / 2, H = N + 1;
-    __shared__ V lds[E::LDS_ELEMS];
-    const int y0 = blockIdx.x * 16;
-    const int z = blockIdx.y;
-    const T* plane = rho + ((size_t)z * N + y0) * N;  // block-uniform base, 32-bit offsets below
-    auto ld = [&](int p, int idx) -> V {
-        const int ya = y0 + 2 * p;
-        const T a = ya < N ? plane[(unsigned)(2 * p * N + idx)] : T(0);
-        const T b = ya + 1 < N ? plane[(unsigned)((2 * p + 1) * N + idx)] : T(0);
-        return V{a, b};
-    };
-    auto st = [&](int p, int idx, V v) { lds[E::lidx(p, idx)] = v; };
-    E::template run<-1, MAP_EF, MAP_MID, MAP_EF, N, P, true>(lds, tw, ld, st, sa);
-    __syncthreads();
-    V* t1z = t1 + (size_t)z * N;
-    for (int e = threadIdx.x; e < 16 * H; e += NT) {
-        const int row = e & 15, k = e >> 4;
-        const int y = y0 + row;
-        if (y >= N) continue;
-        const int p = row >> 1;
-        const V z1 = lds[E::lidx(p, k)];
-        const V z2 = lds[E::lidx(p, k == 0 ? 0 : P - k)];
-        V x;
-        if (row & 1) {
-            x = V{T(0.5) * (z1.y + z2.y), T(-0.5) * (z1.x - z2.x)};
-        } else {
-            x = V{T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
-        }
-        t1z[(unsigned)(k * N * N + y)] = x;
-    }
+    TL::run(blockIdx.x, blockIdx.y, rho, t1, tw, lds, sa);
 }
 
-// ---------------------------------------------------------------------------
-// y_fwd: ZT z-pencils of one kx per workgroup.
-// ---------------------------------------------------------------------------
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* __restrict__ t1, cx<T>* __restrict__ t2,
                                               const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
-    using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ZT, NT, false, MT>;
-    typename E::SA sa;
+    using TL = TileYFwd<T, P, FAM, ZT, NT, MAP_MID, MT>;
+    __shared__ cx<T> lds[TL::LDS];
+    typename TL::E::SA sa;
     sa.load(stab);
-    constexpr int N = P / 2;
-    __shared__ V lds[E::LDS_ELEMS];
-    const int z0 = blockIdx.x * ZT;
-    const int kx = blockIdx.y;
-    const V* in = t1 + ((size_t)kx * N + z0) * N;
-    V* out = t2 + (size_t)kx * P * N + z0;
-    auto ld = [&](int p, int idx) -> V {
-        return z0 + p < N ? in[(unsigned)(p * N + idx)] : V{T(0), T(0)};
-    };
-    auto st = [&](int p, int idx, V v) {
-        if (z0 + p < N) out[(unsigned)(idx * N + p)] = v;
-    };
-    E::template run<-1, MAP_EF, MAP_MID, MAP_PF, N, P>(lds, tw, ld, st, sa);
+    TL::run(blockIdx.x, blockIdx.y, t1, t2, tw, lds, sa);
 }
 
-// ---------------------------------------------------------------------------
-// z_conv: B z-pencils (ky pencils of one kx) per workgroup, in place.
-// WAVE: each wavefront owns its pencils for the whole transform and the stage
-// exchanges synchronise the wavefront only.
-// ---------------------------------------------------------------------------
 template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT>
 __global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* __restrict__ ghat,
                                                const cx<T>* __restrict__ twf, const cx<T>* __restrict__ twi,
                                                const unsigned short* __restrict__ stab)
 {
-    using V = cx<T>;
-    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE, MT>;
-    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE, MT>;
-    typename EF::SA sa;
+    using TL = TileZConv<T, P, FAM, B, NT, WAVE, MT>;
+    __shared__ cx<T> lds[TL::LDS];
+    typename TL::EF::SA sa;
     sa.load(stab);
-    constexpr int MAP_IO = WAVE ? MAP_WV : MAP_EF;
-    constexpr int MAP_MID = MAP_IO, MAP_Z = MAP_IO;
-    static_assert(EF::LDS_ELEMS == EI::LDS_ELEMS, "plans share one LDS buffer");
-    constexpr int N = P / 2, H = N + 1;
-    constexpr int SL = EF::S - 1;
-    __shared__ V lds[EF::LDS_ELEMS];
-    const int q0 = blockIdx.x * B;
-    const int kx = blockIdx.y;
-    V* base = t2 + (size_t)kx * P * N;
-    const T* grow = ghat + (size_t)kx * H * H;
-    // With one pencil per wavefront the pencil index is wavefront-uniform:
-    // keep its row pointers in scalar registers.
-    constexpr bool ONE = WAVE && EF::PPW == 1;
-    const int pw = ONE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
-    const int kyw = z_pencil_ky(q0 + pw, N);
-    V* roww = base + (size_t)kyw * N;
-    const T* growm = grow + (size_t)(kyw <= N ? kyw : P - kyw) * H;
-    auto prow = [&](int p) -> V* { return ONE ? roww : base + (unsigned)(z_pencil_ky(q0 + p, N) * N); };
-    auto ld = [&](int p, int idx) -> V { return prow(p)[idx]; };
-    typename EF::template Regs<SL> g;
-    EF::template run_to_regs<-1, MAP_IO, MAP_MID, MAP_Z, N>(lds, twf, ld, g, sa);
-    // multiply by the real, even transformed kernel at (kz, ky, kx)
-    auto mul = [&](int p, int kz, V& v) {
-        const T* gr;
-        if constexpr (ONE) {
-            gr = growm;
-        } else {
-            const int ky = z_pencil_ky(q0 + p, N);
-            gr = grow + (unsigned)((ky <= N ? ky : P - ky) * H);
-        }
-        const int kf = kz <= N ? kz : P - kz;
-        const T gv = gr[kf];
-        v = V{v.x * gv, v.y * gv};
-    };
-    EF::template for_each_out<SL, MAP_Z>(g, mul);
-    auto st = [&](int p, int idx, V v) { prow(p)[idx] = v; };
-    EI::template run_from_regs<+1, MAP_Z, MAP_MID, MAP_IO, N>(lds, twi, g, st, sa);
+    TL::run(blockIdx.x, blockIdx.y, t2, ghat, twf, twi, lds, sa);
 }
 
-// ---------------------------------------------------------------------------
-// y_inv: ZT z-pencils of one kx per workgroup.
-// ---------------------------------------------------------------------------
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* __restrict__ t2, cx<T>* __restrict__ t1,
                                               const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
-    using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT, false, MT>;
-    typename E::SA sa;
+    using TL = TileYInv<T, P, FAM, ZT, NT, MAP_MID, MT>;
+    __shared__ cx<T> lds[TL::LDS];
+    typename TL::E::SA sa;
     sa.load(stab);
-    constexpr int N = P / 2;
-    __shared__ V lds[E::LDS_ELEMS];
-    const int z0 = blockIdx.x * ZT;
-    const int kx = blockIdx.y;
-    const V* in = t2 + (size_t)kx * P * N + z0;
-    V* out = t1 + ((size_t)kx * N + z0) * N;
-    auto ld = [&](int p, int idx) -> V {
-        return z0 + p < N ? in[(unsigned)(idx * N + p)] : V{T(0), T(0)};
-    };
-    auto st = [&](int p, int idx, V v) {
-        if (z0 + p < N) out[(unsigned)(p * N + idx)] = v;
-    };
-    E::template run<+1, MAP_PF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
+    TL::run(blockIdx.x, blockIdx.y, t2, t1, tw, lds, sa);
 }
 
-// ---------------------------------------------------------------------------
-// x_c2r: 16 rows (8 packed pairs) of one z-plane per workgroup.
-// ---------------------------------------------------------------------------
 template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ t1, T* __restrict__ phi,
                                               const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
-    using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT, false, MT>;
-    typename E::SA sa;
+    using TL = TileXC2R<T, P, FAM, NT, MAP_MID, MT>;
+    __shared__ cx<T> lds[TL::LDS];
+    typename TL::E::SA sa;
     sa.load(stab);
-    constexpr int N = P / 2, H = N + 1;
-    constexpr int XP = H + 1;  // pitch of the staged half spectra
-    constexpr int LDS = E::LDS_ELEMS > 16 * XP ? E::LDS_ELEMS : 16 * XP;
-    __shared__ V lds[LDS];
-    const int y0 = blockIdx.x * 16;
-    const int z = blockIdx.y;
-    const V* t1z = t1 + (size_t)z * N + y0;
-    for (int e = threadIdx.x; e < 16 * H; e += NT) {
-        const int row = e & 15, k = e >> 4;
-        const int y = y0 + row;
-        lds[row * XP + k] = y < N ? t1z[(unsigned)(k * N * N + row)] : V{T(0), T(0)};
-    }
-    __syncthreads();
-    auto ld = [&](int p, int idx) -> V {
-        const V* xa = lds + (2 * p) * XP;
-        const V* xb = xa + XP;
-        V a, b;
-        if (idx <= N) {
-            a = xa[idx];
-            b = xb[idx];
-            if (idx == 0 || idx == N) {
-                a.y = T(0);
-                b.y = T(0);
-            }
-        } else {
-            a = cconj(xa[P - idx]);
-            b = cconj(xb[P - idx]);
-        }
-        return V{a.x - b.y, a.y + b.x};
-    };
-    T* plane = phi + ((size_t)z * N + y0) * N;
-    auto st = [&](int p, int idx, V v) {
-        const int ya = y0 + 2 * p;
-        if (ya < N) plane[(unsigned)(2 * p * N + idx)] = v.x;
-        if (ya + 1 < N) plane[(unsigned)((2 * p + 1) * N + idx)] = v.y;
-    };
-    E::template run<+1, MAP_EF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
+    TL::run(blockIdx.x, blockIdx.y, t1, phi, tw, lds, sa);
 }
 
 }  // namespace ps

@@ -18,6 +18,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_types.hpp"
 #include "ps_internal.hpp"
 
 namespace {
@@ -38,6 +39,27 @@ ps_status device_fail(hipError_t e, const char* where)
 
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Batched-solve control block kept in the workspace of a batch's first plan.
+constexpr int MAX_BATCH = 1024;
+struct BatchLayout {
+    size_t ctl, sol, prefix, done, bytes;
+};
+BatchLayout batch_layout(int ns)
+{
+    BatchLayout L;
+    size_t o = 0;
+    L.ctl = o;
+    o += align_up(sizeof(ps::BatchCtl));
+    L.sol = o;
+    o += align_up((size_t)ns * sizeof(ps::BatchSolve));
+    L.prefix = o;
+    o += align_up((size_t)5 * (ns + 1) * sizeof(int));
+    L.done = o;
+    o += align_up((size_t)ns * 5 * sizeof(unsigned));
+    L.bytes = o;
+    return L;
+}
 
 bool is_plain(ps_precision p) { return p == PS_F64_PLAIN || p == PS_F32_PLAIN; }
 bool is_f64(ps_precision p) { return p == PS_F64 || p == PS_F64_PLAIN; }
@@ -195,7 +217,10 @@ struct ps_plan_s {
     size_t off_t1 = 0, off_t2 = 0;          // pruned intermediates
     size_t off_pad = 0, off_spec = 0;       // plain intermediates
     size_t off_gscr = 0;                    // kernel-build scratch (aliases intermediates)
+    size_t off_batch = 0;                   // batched-solve control block (when first in a batch)
     size_t ws_bytes = 0;
+    std::vector<uintptr_t> batch_sig;       // batch whose work list is in the workspace
+    std::vector<unsigned char> batch_blob;  // host copy of that work list
     // bound state
     unsigned char* ws = nullptr;
     bool ready = false;
@@ -408,6 +433,8 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
         off += align_up(t2);
         p->off_gscr = p->off_t1;
         if (p->off_gscr + gscr > off) off = align_up(p->off_gscr + gscr);
+        p->off_batch = off;
+        off += batch_layout(MAX_BATCH).bytes;
     }
     p->ws_bytes = off;
     *out = p;
@@ -481,6 +508,7 @@ ps_status ps_green_build(ps_plan p, void* d_workspace, double G, double self_coe
     p->G = G;
     p->self_coeff = self_coeff;
     p->ready = true;
+    p->batch_sig.clear();  // a rebuilt plan invalidates any uploaded work list
     return PS_OK;
 }
 
@@ -621,10 +649,125 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
 ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d_rho, void* const* d_phi,
                            void* stream)
 {
-    (void)stream;
     if (!plans || !d_rho || !d_phi) return fail(PS_ERR_INVALID, "plans, rho and phi lists must be non-NULL");
     if (count <= 0) return fail(PS_ERR_INVALID, "count must be positive");
-    return fail(PS_ERR_UNSUPPORTED, "batched solves are not built into this library");
+    if (count > MAX_BATCH) return fail(PS_ERR_UNSUPPORTED, "at most " + std::to_string(MAX_BATCH) + " solves per batch");
+    for (int i = 0; i < count; ++i)
+        if (!plans[i]) return fail(PS_ERR_INVALID, "plan " + std::to_string(i) + " is NULL");
+    const ps_precision prec = plans[0]->prec;
+    if (is_plain(prec)) return fail(PS_ERR_UNSUPPORTED, "batched solves use the pruned pipeline");
+    const int mterms = plans[0]->var.mterms;
+    if (prec == PS_F32_SPLIT && mterms != 6)
+        return fail(PS_ERR_UNSUPPORTED, "batched split solves use the six-term product");
+    for (int i = 0; i < count; ++i) {
+        const ps_plan p = plans[i];
+        const std::string who = "solve " + std::to_string(i);
+        if (p->prec != prec || p->var.mterms != mterms)
+            return fail(PS_ERR_INVALID, who + ": all plans of a batch need the same precision");
+        if (!d_rho[i] || !d_phi[i]) return fail(PS_ERR_INVALID, who + ": rho and phi must be non-NULL");
+        if ((uintptr_t)d_rho[i] % p->real_bytes || (uintptr_t)d_phi[i] % p->real_bytes)
+            return fail(PS_ERR_INVALID, who + ": rho and phi must be aligned to their element size");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == p) return fail(PS_ERR_INVALID, who + ": a plan may appear once per batch");
+    }
+    for (int i = 0; i < count; ++i) {
+        const size_t bi = (size_t)plans[i]->n * plans[i]->n * plans[i]->n * plans[i]->real_bytes;
+        if (overlap(d_rho[i], bi, d_phi[i], bi)) return fail(PS_ERR_INVALID, "rho and phi overlap");
+        for (int j = 0; j < count; ++j) {
+            if (j == i) continue;
+            const size_t bj = (size_t)plans[j]->n * plans[j]->n * plans[j]->n * plans[j]->real_bytes;
+            if (overlap(d_phi[i], bi, d_phi[j], bj) || overlap(d_phi[i], bi, d_rho[j], bj))
+                return fail(PS_ERR_INVALID, "output of solve " + std::to_string(i) + " overlaps another array");
+        }
+    }
+    for (int i = 0; i < count; ++i)
+        if (!plans[i]->ready) return fail(PS_ERR_NOT_READY, "solve " + std::to_string(i) + ": call ps_green_build first");
+    hipStream_t st = (hipStream_t)stream;
+    ps_plan head = plans[0];
+    const BatchLayout L = batch_layout(count);
+    // the work list: solves largest first, pass-major items
+    std::vector<uintptr_t> sig;
+    sig.push_back((uintptr_t)count);
+    for (int i = 0; i < count; ++i) {
+        sig.push_back((uintptr_t)plans[i]);
+        sig.push_back((uintptr_t)d_rho[i]);
+        sig.push_back((uintptr_t)d_phi[i]);
+        sig.push_back((uintptr_t)plans[i]->ws);
+    }
+    if (sig != head->batch_sig) {
+        bool cap = false;
+        hipError_t e;
+        if (!capturing(st, cap, e)) return device_fail(e, "hipStreamIsCapturing");
+        if (cap) return fail(PS_ERR_CAPTURE, "the first call with a new batch uploads its work list; not under capture");
+        std::vector<int> order(count);
+        for (int i = 0; i < count; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plans[a]->P > plans[b]->P; });
+        std::vector<unsigned char> blob(L.bytes, 0);
+        auto* ctl = reinterpret_cast<ps::BatchCtl*>(blob.data() + L.ctl);
+        auto* sol = reinterpret_cast<ps::BatchSolve*>(blob.data() + L.sol);
+        auto* prefix = reinterpret_cast<int*>(blob.data() + L.prefix);
+        int pass_total[5] = {0, 0, 0, 0, 0};
+        for (int k = 0; k < count; ++k) {
+            const ps_plan p = plans[order[k]];
+            ps::BatchSolve& b = sol[k];
+            b.rho = d_rho[order[k]];
+            b.phi = d_phi[order[k]];
+            b.t1 = p->ws + p->off_t1;
+            b.t2 = p->ws + p->off_t2;
+            b.ghat = p->ws + p->off_ghat;
+            b.twf = p->ws + p->off_tab + p->tw_f;
+            b.twi = p->ws + p->off_tab + p->tw_i;
+            b.P = p->P;
+            ps::batch_tiles(p->P, (int)p->real_bytes, b.ntile);
+            for (int ph = 0; ph < 5; ++ph) {
+                prefix[ph * (count + 1) + k] = pass_total[ph];
+                pass_total[ph] += b.ntile[ph];
+            }
+        }
+        for (int ph = 0; ph < 5; ++ph) prefix[ph * (count + 1) + count] = pass_total[ph];
+        ctl->nsolves = count;
+        ctl->pass_begin[0] = 0;
+        for (int ph = 0; ph < 5; ++ph) ctl->pass_begin[ph + 1] = ctl->pass_begin[ph] + pass_total[ph];
+        ctl->total = ctl->pass_begin[5];
+        head->batch_blob.swap(blob);
+        e = hipMemcpyAsync(head->ws + head->off_batch, head->batch_blob.data(), L.bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return device_fail(e, "work list upload");
+        head->batch_sig = sig;
+    }
+    const auto* ctl = reinterpret_cast<const ps::BatchCtl*>(head->batch_blob.data() + L.ctl);
+    int pmax = 0;
+    for (int i = 0; i < count; ++i) pmax = std::max(pmax, plans[i]->P);
+    ps::BatchArgs a;
+    a.kind = prec == PS_F64 ? 2 : (prec == PS_F32_SPLIT ? 1 : 0);
+    a.pmax = pmax;
+    a.ctl = reinterpret_cast<ps::BatchCtl*>(head->ws + head->off_batch + L.ctl);
+    a.sol = reinterpret_cast<const ps::BatchSolve*>(head->ws + head->off_batch + L.sol);
+    a.prefix = reinterpret_cast<const int*>(head->ws + head->off_batch + L.prefix);
+    a.done = reinterpret_cast<unsigned*>(head->ws + head->off_batch + L.done);
+    a.nsolves = count;
+    a.total = ctl->total;
+    a.stab = reinterpret_cast<const unsigned short*>(head->ws + head->off_tab + head->split_tab);
+    a.spin_limit = 1u << 20;
+    a.stream = st;
+    hipError_t e = a.kind == 2 ? ps::batched_run_f64(a) : (a.kind == 1 ? ps::batched_run_split(a) : ps::batched_run_f32(a));
+    if (e != hipSuccess) return device_fail(e, "batched launch");
+    return PS_OK;
+}
+
+ps_status ps_batch_check(ps_plan first, void* stream, int* error)
+{
+    if (ps_status s = check_plan(first)) return s;
+    if (!error) return fail(PS_ERR_INVALID, "error is NULL");
+    if (first->batch_sig.empty()) return fail(PS_ERR_NOT_READY, "this plan has not led a batch");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "batch synchronise");
+    unsigned flag = 0;
+    e = hipMemcpy(&flag, first->ws + first->off_batch + offsetof(ps::BatchCtl, error), sizeof(flag),
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(e, "batch status read");
+    *error = flag ? 1 : 0;
+    return PS_OK;
 }
 
 }  // extern "C"

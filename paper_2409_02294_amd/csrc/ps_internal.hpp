@@ -71,6 +71,25 @@ struct PlainBufs {
 hipError_t plain_run_f32(int P, const PlainBufs& b);
 hipError_t plain_run_f64(int P, const PlainBufs& b);
 
+// One persistent batched launch (plus the reset of its counters).
+struct BatchCtl;
+struct BatchSolve;
+struct BatchArgs {
+    int kind;  // 0 float, 1 float + split-bf16 DFT-16 (6 terms), 2 double
+    int pmax;  // largest padded length in the batch
+    BatchCtl* ctl;
+    const BatchSolve* sol;
+    const int* prefix;
+    unsigned* done;
+    int nsolves, total;
+    const unsigned short* stab;
+    unsigned spin_limit;
+    hipStream_t stream;
+};
+hipError_t batched_run_f32(const BatchArgs& a);
+hipError_t batched_run_split(const BatchArgs& a);
+hipError_t batched_run_f64(const BatchArgs& a);
+
 // Radix plans (forward; the inverse is the reverse) for a supported P and
 // plan family; family 1 falls back to family 0 where it does not exist.
 bool host_radices(int P, std::vector<int>& fwd, int fam = 0);

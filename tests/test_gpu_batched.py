@@ -1,0 +1,167 @@
+"""GPU tests of the persistent batched launch and of HIP-graph capture.
+
+A batch must give every member the result ps_solve gives for the same plan
+(identical per-pencil arithmetic, so bitwise equal with matching kernel
+variants), and a captured graph must replay the eager result bitwise, with
+the program's own eager work and synchronisations between replays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import gpu_available
+from paper_2409_02294_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_2409_02294_amd import solver as S
+
+SAME_VARIANTS = [0, 0, 1, 0, 0]  # the batched kernel's per-length kernel shapes
+
+
+def _make(prec, sizes, seed):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    solvers, rhos = [], []
+    for i, n in enumerate(sizes):
+        s = S.Solver(n, 1.0 / n, prec)
+        for k, v in enumerate(SAME_VARIANTS):
+            S.ps_plan_set_variant(s.plan, k, v)
+        rng = np.random.default_rng(seed + i)
+        blobs = inputs.draw_blobs(rng, int(rng.integers(4, 33)), centre=(0.1, 0.9), sigma=(0.03, 0.08))
+        rho = torch.from_numpy(inputs.blob_density(n, blobs)).to("cuda", dt)
+        solvers.append(s)
+        rhos.append(rho)
+    return solvers, rhos
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "f32_split"])
+def test_batch_matches_single_solves(prec):
+    sizes = [32, 128, 48, 64, 16, 96, 128, 32, 64, 24, 8, 48]
+    solvers, rhos = _make(prec, sizes, 4000)
+    eager = [s(r) for s, r in zip(solvers, rhos)]
+    outs = S.solve_batched(solvers, rhos)
+    st = torch.cuda.current_stream().cuda_stream
+    assert S.ps_batch_check(solvers[0].plan, st) == 0
+    torch.cuda.synchronize()
+    nbit = 0
+    for n, a, b in zip(sizes, outs, eager):
+        err = oracle.rel_l2(a.double().cpu().numpy(), b.double().cpu().numpy())
+        nbit += int(torch.equal(a, b))
+        assert err <= (1e-14 if prec == "f64" else 1e-7), (n, err)
+    print(f"{prec}: {nbit}/{len(sizes)} members bitwise equal to ps_solve", flush=True)
+    assert nbit == len(sizes)
+    # and against the oracle
+    tol = 1e-12 if prec == "f64" else 1e-6
+    for n, a, r in list(zip(sizes, outs, rhos))[:6]:
+        ref = oracle.fft_conv(r.double().cpu().numpy(), 1.0 / n)
+        assert oracle.rel_l2(a.double().cpu().numpy(), ref) <= tol
+
+
+def test_batch_with_large_member():
+    # one length above 256 selects the large-tile persistent kernel
+    sizes = [256, 32, 64, 128]
+    solvers, rhos = _make("f32", sizes, 4100)
+    eager = [s(r) for s, r in zip(solvers, rhos)]
+    outs = S.solve_batched(solvers, rhos)
+    assert S.ps_batch_check(solvers[0].plan, torch.cuda.current_stream().cuda_stream) == 0
+    for n, a, b in zip(sizes, outs, eager):
+        assert oracle.rel_l2(a.double().cpu().numpy(), b.double().cpu().numpy()) <= 1e-7
+
+
+def test_batch_repeat_and_reorder():
+    sizes = [64, 32, 96]
+    solvers, rhos = _make("f32", sizes, 4200)
+    first = [o.clone() for o in S.solve_batched(solvers, rhos)]
+    again = S.solve_batched(solvers, rhos)  # same list: no upload
+    for a, b in zip(first, again):
+        assert torch.equal(a, b)
+    # a different order is a different batch (new work list)
+    rev = S.solve_batched(solvers[::-1], rhos[::-1])
+    for a, b in zip(first, rev[::-1]):
+        assert torch.equal(a, b)
+
+
+def test_batch_argument_errors():
+    solvers, rhos = _make("f32", [16, 16], 4300)
+    lib = S.load()
+    with pytest.raises(S.PSError) as e:
+        S.ps_solve_batched([solvers[0].plan, solvers[0].plan], [rhos[0].data_ptr()] * 2,
+                           [torch.empty_like(rhos[0]).data_ptr(), torch.empty_like(rhos[0]).data_ptr()], 0)
+    assert e.value.status == S.PS_ERR_INVALID
+    out = torch.empty_like(rhos[0])
+    with pytest.raises(S.PSError) as e:  # both outputs in the same array
+        S.ps_solve_batched([s.plan for s in solvers], [r.data_ptr() for r in rhos], [out.data_ptr()] * 2, 0)
+    assert e.value.status == S.PS_ERR_INVALID
+    f64 = S.Solver(16, 1.0 / 16, "f64")
+    with pytest.raises(S.PSError) as e:  # mixed arithmetic
+        S.ps_solve_batched([solvers[0].plan, f64.plan], [rhos[0].data_ptr(), rhos[1].data_ptr()],
+                           [torch.empty_like(rhos[0]).data_ptr(), torch.empty(16 ** 3, dtype=torch.float64, device="cuda").data_ptr()], 0)
+    assert e.value.status == S.PS_ERR_INVALID
+
+
+def _replay_check(g, outs, eager, work):
+    for rep in range(3):
+        work()  # eager work of the program between replays
+        torch.cuda.synchronize()
+        for o in outs:
+            o.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), f"replay {rep} differs"
+
+
+def test_graph_replay_single_solve():
+    n = 64
+    s = S.Solver(n, 1.0 / n, "f32")
+    rho = torch.from_numpy(inputs.make_density(n, 8, 11, sigma=(0.03, 0.08))).to("cuda", torch.float32)
+    out = torch.empty_like(rho)
+    s(rho, out)
+    torch.cuda.synchronize()
+    eager = out.clone()
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        s(rho, out)  # warm-up on the capture stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            s.solve(rho, out)
+    _replay_check(g, [out], [eager], lambda: s(rho * 2.0))
+
+
+def test_graph_replay_batched():
+    sizes = [32, 48, 64, 96, 128, 32, 64]
+    solvers, rhos = _make("f32", sizes, 4400)
+    outs = [torch.empty_like(r) for r in rhos]
+    S.solve_batched(solvers, rhos, outs)  # first call uploads the work list
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        S.solve_batched(solvers, rhos, outs)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            S.solve_batched(solvers, rhos, outs)
+    _replay_check(g, outs, eager, lambda: [s(r) for s, r in zip(solvers, rhos)])
+    assert S.ps_batch_check(solvers[0].plan, torch.cuda.current_stream().cuda_stream) == 0
+
+
+def test_capture_of_new_batch_is_refused():
+    sizes = [32, 16]
+    solvers, rhos = _make("f32", sizes, 4500)
+    outs = [torch.empty_like(r) for r in rhos]
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    status = None
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            outs[0].add_(1.0)
+            try:
+                S.solve_batched(solvers, rhos, outs)
+            except S.PSError as e:
+                status = e.status
+    assert status == S.PS_ERR_CAPTURE
