@@ -44,13 +44,7 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
-def _load() -> ctypes.CDLL:
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = ctypes.CDLL(_LIB_PATH)
+def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
     i, d = ctypes.c_int, ctypes.c_double
@@ -71,8 +65,17 @@ def _load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    _lib = lib
     return lib
+
+
+def _load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
 
 
 def _dp(a: np.ndarray):
@@ -91,84 +94,116 @@ def _cube(rho: np.ndarray) -> np.ndarray:
     return rho
 
 
-def set_threads(n: int) -> int:
-    return _load().or_set_threads(int(n))
+class Oracle:
+    """The oracle's functions bound to one build of ``oracle.c``."""
+
+    def __init__(self, lib: Optional[ctypes.CDLL] = None):
+        self._l = lib
+
+    @property
+    def lib(self) -> ctypes.CDLL:
+        return self._l if self._l is not None else _load()
+
+    def set_threads(self, n: int) -> int:
+        return self.lib.or_set_threads(int(n))
+
+    def get_threads(self) -> int:
+        return self.lib.or_get_threads()
+
+    def kernel_value(self, di: int, dj: int, dk: int, dx: float, self_coeff: float = SELF_COEFF) -> float:
+        return self.lib.or_kernel_value(int(di), int(dj), int(dk), float(dx), float(self_coeff))
+
+    def direct_sum(self, rho: np.ndarray, dx: float, G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = _cube(rho)
+        phi = np.empty_like(rho)
+        _check(self.lib.or_direct_sum(rho.shape[0], dx, G, self_coeff, _dp(rho), _dp(phi)), "direct_sum")
+        return phi
+
+    def direct_sum_cells(self, rho: np.ndarray, cells: Sequence[Sequence[int]], dx: float, G: float = 1.0,
+                         self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = _cube(rho)
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+        out = np.empty(c.shape[0], dtype=np.float64)
+        rc = self.lib.or_direct_sum_cells(rho.shape[0], dx, G, self_coeff, _dp(rho), int(c.shape[0]),
+                                          c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out))
+        _check(rc, "direct_sum_cells")
+        return out
+
+    def fft(self, x: np.ndarray, sign: int = -1) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.complex128).ravel()
+        out = np.empty_like(x)
+        _check(self.lib.or_fft(int(x.shape[0]), _dp(x.view(np.float64)), _dp(out.view(np.float64)), sign), "fft")
+        return out
+
+    def fft3(self, a: np.ndarray, sign: int = -1) -> np.ndarray:
+        a = np.array(a, dtype=np.complex128, order="C", copy=True)
+        if a.ndim != 3 or len(set(a.shape)) != 1:
+            raise ValueError("fft3 needs a cubic array")
+        _check(self.lib.or_fft3(int(a.shape[0]), _dp(a.view(np.float64)), sign), "fft3")
+        return a
+
+    def kernel_pad(self, n: int, dx: float, self_coeff: float = SELF_COEFF) -> np.ndarray:
+        p = 2 * n
+        k = np.empty((p, p, p), dtype=np.float64)
+        _check(self.lib.or_kernel_pad(n, dx, self_coeff, _dp(k)), "kernel_pad")
+        return k
+
+    def green_hat(self, n: int, dx: float, self_coeff: float = SELF_COEFF) -> np.ndarray:
+        p = 2 * n
+        g = np.empty((p, p, p), dtype=np.complex128)
+        _check(self.lib.or_green_hat(n, dx, self_coeff, _dp(g.view(np.float64))), "green_hat")
+        return g
+
+    def fft_conv_kernel(self, rho: np.ndarray, kpad: np.ndarray, dx: float, G: float = 1.0) -> np.ndarray:
+        rho = _cube(rho)
+        n = rho.shape[0]
+        kpad = np.ascontiguousarray(kpad, dtype=np.float64)
+        if kpad.shape != (2 * n,) * 3:
+            raise ValueError("kpad must be (2N)^3")
+        phi = np.empty_like(rho)
+        _check(self.lib.or_fft_conv_kernel(n, dx, G, _dp(kpad), _dp(rho), _dp(phi)), "fft_conv_kernel")
+        return phi
+
+    def fft_conv(self, rho: np.ndarray, dx: float, G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = _cube(rho)
+        phi = np.empty_like(rho)
+        _check(self.lib.or_fft_conv(rho.shape[0], dx, G, self_coeff, _dp(rho), _dp(phi)), "fft_conv")
+        return phi
+
+    @staticmethod
+    def rel_l2(a, ref):
+        return rel_l2(a, ref)
+
+    @staticmethod
+    def rel_max(a, ref):
+        return rel_max(a, ref)
 
 
-def get_threads() -> int:
-    return _load().or_get_threads()
+def variant(so_path: str) -> Oracle:
+    """An :class:`Oracle` bound to another build of ``oracle.c`` (used by the
+    tests that plant mistakes in the oracle to check that the pins catch them)."""
+    return Oracle(_bind(ctypes.CDLL(so_path)))
 
 
-def kernel_value(di: int, dj: int, dk: int, dx: float, self_coeff: float = SELF_COEFF) -> float:
-    return _load().or_kernel_value(int(di), int(dj), int(dk), float(dx), float(self_coeff))
+def build_variant(out_path: str, defines: Sequence[str] = ()) -> str:
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", *[f"-D{d}" for d in defines],
+           "-o", out_path, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
 
 
-def direct_sum(rho: np.ndarray, dx: float, G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
-    rho = _cube(rho)
-    n = rho.shape[0]
-    phi = np.empty_like(rho)
-    _check(_load().or_direct_sum(n, dx, G, self_coeff, _dp(rho), _dp(phi)), "direct_sum")
-    return phi
-
-
-def direct_sum_cells(rho: np.ndarray, cells: Sequence[Sequence[int]], dx: float, G: float = 1.0,
-                     self_coeff: float = SELF_COEFF) -> np.ndarray:
-    rho = _cube(rho)
-    n = rho.shape[0]
-    c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
-    out = np.empty(c.shape[0], dtype=np.float64)
-    rc = _load().or_direct_sum_cells(n, dx, G, self_coeff, _dp(rho), int(c.shape[0]),
-                                     c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out))
-    _check(rc, "direct_sum_cells")
-    return out
-
-
-def fft(x: np.ndarray, sign: int = -1) -> np.ndarray:
-    x = np.ascontiguousarray(x, dtype=np.complex128).ravel()
-    out = np.empty_like(x)
-    _check(_load().or_fft(int(x.shape[0]), _dp(x.view(np.float64)), _dp(out.view(np.float64)), sign), "fft")
-    return out
-
-
-def fft3(a: np.ndarray, sign: int = -1) -> np.ndarray:
-    a = np.array(a, dtype=np.complex128, order="C", copy=True)
-    if a.ndim != 3 or len(set(a.shape)) != 1:
-        raise ValueError("fft3 needs a cubic array")
-    _check(_load().or_fft3(int(a.shape[0]), _dp(a.view(np.float64)), sign), "fft3")
-    return a
-
-
-def kernel_pad(n: int, dx: float, self_coeff: float = SELF_COEFF) -> np.ndarray:
-    p = 2 * n
-    k = np.empty((p, p, p), dtype=np.float64)
-    _check(_load().or_kernel_pad(n, dx, self_coeff, _dp(k)), "kernel_pad")
-    return k
-
-
-def green_hat(n: int, dx: float, self_coeff: float = SELF_COEFF) -> np.ndarray:
-    p = 2 * n
-    g = np.empty((p, p, p), dtype=np.complex128)
-    _check(_load().or_green_hat(n, dx, self_coeff, _dp(g.view(np.float64))), "green_hat")
-    return g
-
-
-def fft_conv_kernel(rho: np.ndarray, kpad: np.ndarray, dx: float, G: float = 1.0) -> np.ndarray:
-    rho = _cube(rho)
-    n = rho.shape[0]
-    kpad = np.ascontiguousarray(kpad, dtype=np.float64)
-    if kpad.shape != (2 * n,) * 3:
-        raise ValueError("kpad must be (2N)^3")
-    phi = np.empty_like(rho)
-    _check(_load().or_fft_conv_kernel(n, dx, G, _dp(kpad), _dp(rho), _dp(phi)), "fft_conv_kernel")
-    return phi
-
-
-def fft_conv(rho: np.ndarray, dx: float, G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
-    rho = _cube(rho)
-    n = rho.shape[0]
-    phi = np.empty_like(rho)
-    _check(_load().or_fft_conv(n, dx, G, self_coeff, _dp(rho), _dp(phi)), "fft_conv")
-    return phi
+_default = Oracle()
+set_threads = _default.set_threads
+get_threads = _default.get_threads
+kernel_value = _default.kernel_value
+direct_sum = _default.direct_sum
+direct_sum_cells = _default.direct_sum_cells
+fft = _default.fft
+fft3 = _default.fft3
+kernel_pad = _default.kernel_pad
+green_hat = _default.green_hat
+fft_conv_kernel = _default.fft_conv_kernel
+fft_conv = _default.fft_conv
 
 
 def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:

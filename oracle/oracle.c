@@ -53,6 +53,14 @@
 
 typedef double complex cplx;
 
+/* Planted-mistake builds for the tests that check the pins catch mistakes:
+ * compiled with -DORACLE_MUTATION=k, one deliberate error is switched on.
+ * The default build (0) has none. */
+#ifndef ORACLE_MUTATION
+#define ORACLE_MUTATION 0
+#endif
+#define MUT(k) (ORACLE_MUTATION == (k))
+
 #define OR_OK 0
 #define OR_ERR_ARG (-1)
 #define OR_ERR_NOMEM (-2)
@@ -82,8 +90,9 @@ int or_get_threads(void)
 /* K(d) for an integer displacement (di, dj, dk). */
 double or_kernel_value(long di, long dj, long dk, double dx, double self_coeff)
 {
-    if (di == 0 && dj == 0 && dk == 0) return -self_coeff / dx;
+    if (di == 0 && dj == 0 && dk == 0) return MUT(1) ? self_coeff / dx : -self_coeff / dx;
     double r2 = (double)(di * di) + (double)(dj * dj) + (double)(dk * dk);
+    if (MUT(10)) return -1.0 / (dx * r2);
     return -1.0 / (dx * sqrt(r2));
 }
 
@@ -118,7 +127,10 @@ static double direct_one(int n, const double *ktab, const double *rho, int iz, i
             const double *kr = ktab + ((size_t)az * n + ay) * n;
             const double *rr = rho + ((size_t)jz * n + jy) * n;
             double row = 0.0;
-            for (int jx = 0; jx < n; ++jx) row += kr[abs(ix - jx)] * rr[jx];
+            for (int jx = 0; jx < n; ++jx) {
+                if (MUT(6) && az == 0 && ay == 0 && jx == ix) continue;
+                row += kr[abs(ix - jx)] * rr[jx];
+            }
             const double t = sum + row;
             if (fabs(sum) >= fabs(row)) comp += (sum - t) + row;
             else comp += (row - t) + sum;
@@ -217,7 +229,11 @@ static void fft_rec(int n, const cplx *in, long stride, cplx *out, cplx *scratch
         for (int s = 0; s < p; ++s) {
             const long kk = k + (long)s * m;
             cplx acc = 0.0;
-            for (int q = 0; q < p; ++q) acc += out[(long)q * m + k] * tw[(((long)q * kk) % n) * step];
+            for (int q = 0; q < p; ++q) {
+                long e = ((long)q * (MUT(9) ? k : kk)) % n;
+                if (MUT(3) && p == 2) e = (n - e) % n;
+                acc += out[(long)q * m + k] * tw[e * step];
+            }
             scratch[kk] = acc;
         }
     memcpy(out, scratch, (size_t)n * sizeof(cplx));
@@ -250,7 +266,7 @@ static int fft3_inplace(int p, cplx *a, int sign)
     if (!tw) return OR_ERR_NOMEM;
     const long pp = (long)p * p;
     int err = 0;
-    for (int axis = 0; axis < 3; ++axis) {
+    for (int axis = 0; axis < (MUT(7) ? 2 : 3); ++axis) {
         const long stride = axis == 0 ? 1 : (axis == 1 ? p : pp);
 #pragma omp parallel
         {
@@ -299,7 +315,8 @@ int or_kernel_pad(int n, double dx, double self_coeff, double *kpad)
     for (long z = 0; z < p; ++z)
         for (long y = 0; y < p; ++y)
             for (long x = 0; x < p; ++x) {
-                const long dz = z < p - z ? z : p - z, dy = y < p - y ? y : p - y, dxx = x < p - x ? x : p - x;
+                const long w = MUT(2) ? p - 1 : p;
+                const long dz = z < p - z ? z : w - z, dy = y < p - y ? y : w - y, dxx = x < p - x ? x : w - x;
                 kpad[(z * p + y) * p + x] = or_kernel_value(dxx, dy, dz, dx, self_coeff);
             }
     return OR_OK;
@@ -348,11 +365,14 @@ int or_fft_conv_kernel(int n, double dx, double g, const double *kpad, const dou
         rc = fft3_inplace(p, a, +1);
     }
     if (!rc) {
-        const double scale = g * dx * dx * dx / (double)m;
+        double scale = g * dx * dx * dx / (double)m;
+        if (MUT(4)) scale = g * dx * dx * dx;
+        if (MUT(5)) scale = g * dx * dx / (double)m;
 #pragma omp parallel for schedule(static)
         for (long z = 0; z < n; ++z)
             for (long y = 0; y < n; ++y)
-                for (long x = 0; x < n; ++x) phi[(z * n + y) * n + x] = scale * creal(a[(z * p + y) * p + x]);
+                for (long x = 0; x < n; ++x)
+                    phi[(z * n + y) * n + x] = scale * creal(a[(z * p + y) * p + x + (MUT(8) ? 1 : 0)]);
     }
     free(a);
     free(k);
