@@ -33,8 +33,8 @@ METRIC = "Poisson solves/s + HBM GB/s at 512^3, FP32-split vs FP64, at rel-L2 <=
 def pass_bytes(n: int, rb: int):
     """Algorithmic HBM bytes per launch of each pass (read + write, once each)."""
     p, h, cb = 2 * n, n + 1, 2 * rb
-    t1 = h * n * n * cb
-    t2 = h * p * n * cb
+    t1 = h * n * n * cb          # T1 and the used part of T4
+    t2 = h * p * n * cb          # T2 and T3
     return {
         "x_r2c": n ** 3 * rb + t1,
         "y_fwd": t1 + t2,
@@ -104,8 +104,8 @@ def time_passes(torch, S, s, rho, phi, steps):
     on the stream they are launched on."""
     info = s.info()
     ws = s.workspace.data_ptr()
-    t1, t2 = ws + info["t1_offset"], ws + info["t2_offset"]
-    io = [(rho.data_ptr(), t1), (t1, t2), (t2, t2), (t2, t1), (t1, phi.data_ptr())]
+    t1, t2, t3 = ws + info["t1_offset"], ws + info["t2_offset"], ws + info["t3_offset"]
+    io = [(rho.data_ptr(), t1), (t1, t2), (t2, t3), (t3, t1), (t1, phi.data_ptr())]
     stream = torch.cuda.current_stream().cuda_stream
     tot = [0.0] * 5
     for it in range(steps + 1):

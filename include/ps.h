@@ -74,8 +74,9 @@ typedef struct {
     size_t ghat_bytes;      /* bytes of the stored kernel spectrum (real octant) */
     int ready;              /* 1 after a successful ps_green_build */
     int radices[8];         /* forward radix plan, 0-terminated */
-    size_t t1_offset;       /* byte offset in the workspace of T1/T4 (pruned plans; 0 otherwise) */
-    size_t t2_offset;       /* byte offset in the workspace of T2/T3 (pruned plans; 0 otherwise) */
+    size_t t1_offset;       /* byte offset in the workspace of T1 and T4 (pruned plans; 0 otherwise) */
+    size_t t2_offset;       /* byte offset in the workspace of T2 (pruned plans; 0 otherwise) */
+    size_t t3_offset;       /* byte offset in the workspace of T3 (pruned plans; 0 otherwise) */
     int variant[5];         /* kernel variant of each pruned pass (see ps_plan_set_variant) */
     int split_terms;        /* PS_F32_SPLIT: split-bf16 product terms per DFT-16 (6 or 3); else 0 */
 } ps_plan_info;
@@ -156,13 +157,15 @@ const char *ps_status_str(ps_status s);
 const char *ps_last_error(void);
 
 /* Test hook: run a single pass of the pruned pipeline of a built plan on
- * caller arrays, in the layouts the pipeline uses between passes
- * (H = n + 1, P = 2n; complex = interleaved re, im of the plan's type):
- *   pass 0  x R2C   in rho[z][y][x] (n^3 real)      -> out T1[kx][z][y] (H n n complex)
- *   pass 1  y fwd   in T1                           -> out T2[kx][ky][z] (H P n complex)
- *   pass 2  z conv  in T2 -> out T2 (in may equal out), forward z FFT, product, inverse, crop
- *   pass 3  y inv   in T2                           -> out T1
- *   pass 4  x C2R   in T1                           -> out phi[z][y][x]
+ * caller arrays (in != out), in the layouts the pipeline uses between passes
+ * (H = n + 1, P = 2n, HP = H rounded up to a multiple of 16; complex =
+ * interleaved re, im of the plan's type):
+ *   pass 0  x R2C   in rho[z][y][x] (n^3 real)  -> out T1[kx][z][y]  (H n n complex)
+ *   pass 1  y fwd   in T1                       -> out T2[kx][ky][z] (H P n complex)
+ *   pass 2  z conv  in T2 -> forward z FFT, product with the kernel, inverse, crop
+ *                                               -> out T3[kx][z][ky] (H n P complex)
+ *   pass 3  y inv   in T3                       -> out T4[z][y][kx]  (n n HP complex, kx < H used)
+ *   pass 4  x C2R   in T4                       -> out phi[z][y][x]
  * Not for PLAIN precisions (PS_ERR_UNSUPPORTED). */
 ps_status ps_debug_pass(ps_plan p, int pass, const void *d_in, void *d_out, void *stream);
 

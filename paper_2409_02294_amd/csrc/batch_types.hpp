@@ -10,6 +10,7 @@ struct BatchSolve {
     void* phi;
     void* t1;
     void* t2;
+    void* t3;
     const void* ghat;
     const void* twf;
     const void* twi;
@@ -34,7 +35,7 @@ __host__ __device__ inline void batch_tiles(int P, int real_bytes, int out[5])
     out[0] = ((N + 15) / 16) * N;
     out[1] = ((N + ZT - 1) / ZT) * H;
     out[2] = (P / ZT) * H;
-    out[3] = ((N + ZT - 1) / ZT) * H;
+    out[3] = ((H + ZT - 1) / ZT) * N;
     out[4] = ((N + 15) / 16) * N;
 }
 

@@ -179,9 +179,11 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
     static_assert(!WSYNC || (NT % 64 == 0 && B % NW == 0 && PPW >= 1), "wave-owned pencils need B divisible by waves");
     static_assert(MT == 0 || NT % 64 == 0, "matrix-core stages need whole wavefronts");
 
-    __device__ __forceinline__ static void sync()
+    // Barrier between an LDS phase with mapping MA and one with mapping MB:
+    // wavefront-level only when both keep every pencil inside one wavefront.
+    template <int MA, int MB> __device__ __forceinline__ static void sync2()
     {
-        if constexpr (WSYNC) {
+        if constexpr (WSYNC && MA == MAP_WV && MB == MAP_WV) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -409,20 +411,23 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
         }
     }
 
-    // Middle stages [S0, S1) through LDS with mapping MAP.
-    template <int s, int S1, int DIR, int MAP>
+    // Middle stages [S0, S1) through LDS with mapping MAP; MPREV is the
+    // mapping of the stage that wrote the LDS before stage S0.
+    template <int s, int S1, int DIR, int MAP, int MPREV>
     __device__ __forceinline__ static void middle(V* lds, const V* tw, const SA& sa)
     {
         if constexpr (s < S1) {
             Regs<s> g;
-            sync();
+            sync2<MPREV, MAP>();
             load_lds<s, MAP>(g, lds);
             compute<s, DIR, MAP>(g, tw, sa);
-            sync();
+            sync2<MAP, MAP>();
             store_lds<s, MAP>(g, lds);
-            middle<s + 1, S1, DIR, MAP>(lds, tw, sa);
+            middle<s + 1, S1, DIR, MAP, MAP>(lds, tw, sa);
         }
     }
+    // mapping of the stage that writes the LDS read by the last stage
+    template <int MAP_IN, int MAP_MID> static constexpr int map_before_last = S > 2 ? MAP_MID : MAP_IN;
 
     // Full transform: loader -> stages -> storer.  DST_LDS: the storer writes
     // into the same LDS buffer, so a barrier separates the last reads from
@@ -435,15 +440,15 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
             load_first<MAP_IN, LIN>(g, ld);
             compute<0, DIR, MAP_IN>(g, tw, sa);
             if constexpr (MAP_IN == MAP_OUT) {
-                if constexpr (DST_LDS) sync();
+                if constexpr (DST_LDS) __syncthreads();
                 store_last<MAP_OUT, LOUT>(g, st);
             } else {
                 // one stage but different access patterns on the two sides:
                 // go through LDS in natural order
                 static_assert(!DST_LDS, "LDS destination needs matching mappings");
-                sync();
+                __syncthreads();
                 store_lds<0, MAP_IN>(g, lds);
-                sync();
+                __syncthreads();
                 for (int e = threadIdx.x; e < B * LOUT; e += NT) {
                     int p, idx;
                     if constexpr (MAP_OUT == MAP_PF) {
@@ -461,16 +466,16 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
                 Regs<0> g;
                 load_first<MAP_IN, LIN>(g, ld);
                 compute<0, DIR, MAP_IN>(g, tw, sa);
-                sync();
+                sync2<MAP_IN, MAP_IN>();
                 store_lds<0, MAP_IN>(g, lds);
             }
-            middle<1, S - 1, DIR, MAP_MID>(lds, tw, sa);
+            middle<1, S - 1, DIR, MAP_MID, MAP_IN>(lds, tw, sa);
             {
                 Regs<S - 1> g;
-                sync();
+                sync2<map_before_last<MAP_IN, MAP_MID>, MAP_OUT>();
                 load_lds<S - 1, MAP_OUT>(g, lds);
                 compute<S - 1, DIR, MAP_OUT>(g, tw, sa);
-                if constexpr (DST_LDS) sync();
+                if constexpr (DST_LDS) __syncthreads();
                 store_last<MAP_OUT, LOUT>(g, st);
             }
         }
@@ -491,11 +496,11 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
                 Regs<0> g;
                 load_first<MAP_IN, LIN>(g, ld);
                 compute<0, DIR, MAP_IN>(g, tw, sa);
-                sync();
+                sync2<MAP_IN, MAP_IN>();
                 store_lds<0, MAP_IN>(g, lds);
             }
-            middle<1, S - 1, DIR, MAP_MID>(lds, tw, sa);
-            sync();
+            middle<1, S - 1, DIR, MAP_MID, MAP_IN>(lds, tw, sa);
+            sync2<map_before_last<MAP_IN, MAP_MID>, MAP_OUT>();
             load_lds<S - 1, MAP_OUT>(out, lds);
             compute<S - 1, DIR, MAP_OUT>(out, tw, sa);
         }
@@ -508,17 +513,34 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
                                                          const SA& sa = SA{})
     {
         if constexpr (S == 1) {
-            static_assert(MAP_IN == MAP_OUT, "single-stage plans need one mapping");
             compute<0, DIR, MAP_IN>(g, tw, sa);
-            store_last<MAP_OUT, LOUT>(g, st);
+            if constexpr (MAP_IN == MAP_OUT) {
+                store_last<MAP_OUT, LOUT>(g, st);
+            } else {
+                // one stage, different output pattern: through LDS in natural order
+                __syncthreads();
+                store_lds<0, MAP_IN>(g, lds);
+                __syncthreads();
+                for (int e = threadIdx.x; e < B * LOUT; e += NT) {
+                    int p, idx;
+                    if constexpr (MAP_OUT == MAP_PF) {
+                        p = e % B;
+                        idx = e / B;
+                    } else {
+                        idx = e % LOUT;
+                        p = e / LOUT;
+                    }
+                    st(p, idx, lds[lidx(p, idx)]);
+                }
+            }
         } else {
             compute<0, DIR, MAP_IN>(g, tw, sa);
-            sync();
+            sync2<MAP_IN, MAP_IN>();
             store_lds<0, MAP_IN>(g, lds);
-            middle<1, S - 1, DIR, MAP_MID>(lds, tw, sa);
+            middle<1, S - 1, DIR, MAP_MID, MAP_IN>(lds, tw, sa);
             {
                 Regs<S - 1> h;
-                sync();
+                sync2<map_before_last<MAP_IN, MAP_MID>, MAP_OUT>();
                 load_lds<S - 1, MAP_OUT>(h, lds);
                 compute<S - 1, DIR, MAP_OUT>(h, tw, sa);
                 store_last<MAP_OUT, LOUT>(h, st);

@@ -52,12 +52,13 @@ template <typename T, int P, int NT, int MT> struct BatchTiles {
         }
         case 2: {
             constexpr int nq = P / ZT;
-            TZ::run(tile % nq, tile / nq, static_cast<V*>(s.t2), static_cast<const T*>(s.ghat), twf, twi, lds, sa);
+            TZ::run(tile % nq, tile / nq, static_cast<const V*>(s.t2), static_cast<V*>(s.t3),
+                    static_cast<const T*>(s.ghat), twf, twi, lds, sa);
             break;
         }
         case 3: {
-            constexpr int nz = (N + ZT - 1) / ZT;
-            TI::run(tile % nz, tile / nz, static_cast<const V*>(s.t2), static_cast<V*>(s.t1), twi, lds, sa);
+            constexpr int nk = (N + 1 + ZT - 1) / ZT;
+            TI::run(tile % nk, tile / nk, static_cast<const V*>(s.t3), static_cast<V*>(s.t1), twi, lds, sa);
             break;
         }
         default: {

@@ -3,15 +3,19 @@
 //
 //   x_r2c   rho[z][y][x]  (N^3 real)      -> T1[kx][z][y]  (H x N x N complex)
 //   y_fwd   T1[kx][z][y]                  -> T2[kx][ky][z] (H x P x N complex)
-//   z_conv  T2[kx][ky][z] -> forward z FFT -> * Ghat -> inverse z FFT -> T2 (in place)
-//   y_inv   T2[kx][ky][z]                 -> T1[kx][z][y]  (inverse along y, y < N kept)
-//   x_c2r   T1[kx][z][y]                  -> phi[z][y][x]  (inverse real FFT, x < N kept)
+//   z_conv  T2[kx][ky][z] -> forward z FFT -> * Ghat -> inverse z FFT
+//                                         -> T3[kx][z][ky] (H x N x P complex)
+//   y_inv   T3[kx][z][ky]                 -> T4[z][y][kx]  (N x N x HP complex, inverse
+//                                            along y, y < N kept; row pitch HP = H rounded
+//                                            up to 16)
+//   x_c2r   T4[z][y][kx]                  -> phi[z][y][x]  (inverse real FFT, x < N kept)
 //
 // The zero padding to P is never stored: the first stage of every forward
 // transform treats inputs >= N as zeros, and the last stage of every inverse
-// transform produces only outputs < N (the crop).  Each intermediate is laid
-// out so that one pass reads whole contiguous pencils and the next reads
-// 16-pencil tiles (128 bytes per row in FP32) of interleaved pencils.
+// transform produces only outputs < N (the crop).  Every pass reads whole
+// contiguous pencils and writes its output as rows of 16 interleaved pencils
+// (128 bytes in FP32, 8 pencils in FP64), the access pattern HBM serves best
+// in both directions on MI355X.
 //
 // Real transforms along x pack two density rows into one complex pencil
 // (row a + i row b); the two half spectra separate by Hermitian symmetry,
@@ -27,15 +31,9 @@
 
 namespace ps {
 
-// Ordering of the P ky pencils for the z pass: ky 0 and N first, then the
-// pairs (i, P - i) next to each other so that a workgroup holding both reads
-// their shared Ghat row once.
-__device__ __forceinline__ int z_pencil_ky(int q, int N)
-{
-    const int i = q >> 1;
-    const int odd = i == 0 ? N : 2 * N - i;
-    return (q & 1) ? odd : i;
-}
+// Row pitch (complex elements) of T4: H rounded up to 16 so that the rows of
+// interleaved pencils written by y_inv start 128-byte aligned.
+__host__ __device__ constexpr int t4_pitch(int H) { return (H + 15) / 16 * 16; }
 
 // Each pass is a tile function (one workgroup's share, addressed by tile
 // coordinates, using a caller-provided LDS buffer of at least LDS elements),
@@ -110,9 +108,10 @@ template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struc
 };
 
 // ---------------------------------------------------------------------------
-// z_conv: B z-pencils (ky pencils of one kx), in place; tile (ky-tile bx, kx by).
-// WAVE: each wavefront owns its pencils for the whole transform and the stage
-// exchanges synchronise the wavefront only.
+// z_conv: B consecutive ky pencils of one kx; tile (ky-tile bx, kx by).
+// WAVE: each wavefront owns its pencils through every stage but the last,
+// and those stage exchanges synchronise the wavefront only; the last stage
+// spans the workgroup so its stores form rows of B interleaved pencils.
 // ---------------------------------------------------------------------------
 template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT> struct TileZConv {
     using V = cx<T>;
@@ -121,69 +120,55 @@ template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT> struct T
     static_assert(EF::LDS_ELEMS == EI::LDS_ELEMS, "plans share one LDS buffer");
     static constexpr int N = P / 2, H = N + 1;
     static constexpr int LDS = EF::LDS_ELEMS;
-    __device__ __forceinline__ static void run(int bx, int by, V* __restrict__ t2, const T* __restrict__ ghat,
-                                               const V* __restrict__ twf, const V* __restrict__ twi, V* lds,
-                                               const typename EF::SA& sa)
+    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t2, V* __restrict__ t3,
+                                               const T* __restrict__ ghat, const V* __restrict__ twf,
+                                               const V* __restrict__ twi, V* lds, const typename EF::SA& sa)
     {
         constexpr int MAP_IO = WAVE ? MAP_WV : MAP_EF;
-        constexpr int MAP_MID = MAP_IO, MAP_Z = MAP_IO;
         constexpr int SL = EF::S - 1;
-        const int q0 = bx * B;
+        const int ky0 = bx * B;
         const int kx = by;
-        V* base = t2 + (size_t)kx * P * N;
+        const V* in = t2 + ((size_t)kx * P + ky0) * N;  // pencil p at in + p N
+        V* out = t3 + (size_t)kx * N * P + ky0;         // element (z, p) at out[z P + p]
         const T* grow = ghat + (size_t)kx * H * H;
-        // With one pencil per wavefront the pencil index is wavefront-uniform:
-        // keep its row pointers in scalar registers.
-        constexpr bool ONE = WAVE && EF::PPW == 1;
-        const int pw = ONE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
-        const int kyw = z_pencil_ky(q0 + pw, N);
-        V* roww = base + (size_t)kyw * N;
-        const T* growm = grow + (size_t)(kyw <= N ? kyw : P - kyw) * H;
-        auto prow = [&](int p) -> V* { return ONE ? roww : base + (unsigned)(z_pencil_ky(q0 + p, N) * N); };
-        auto ld = [&](int p, int idx) -> V { return prow(p)[idx]; };
+        auto ld = [&](int p, int idx) -> V { return in[(unsigned)(p * N + idx)]; };
         typename EF::template Regs<SL> g;
-        EF::template run_to_regs<-1, MAP_IO, MAP_MID, MAP_Z, N>(lds, twf, ld, g, sa);
+        EF::template run_to_regs<-1, MAP_IO, MAP_IO, MAP_IO, N>(lds, twf, ld, g, sa);
         // multiply by the real, even transformed kernel at (kz, ky, kx)
         auto mul = [&](int p, int kz, V& v) {
-            const T* gr;
-            if constexpr (ONE) {
-                gr = growm;
-            } else {
-                const int ky = z_pencil_ky(q0 + p, N);
-                gr = grow + (unsigned)((ky <= N ? ky : P - ky) * H);
-            }
-            const int kf = kz <= N ? kz : P - kz;
-            const T gv = gr[kf];
+            const int ky = ky0 + p;
+            const T* gr = grow + (unsigned)((ky <= N ? ky : P - ky) * H);
+            const T gv = gr[kz <= N ? kz : P - kz];
             v = V{v.x * gv, v.y * gv};
         };
-        EF::template for_each_out<SL, MAP_Z>(g, mul);
-        auto st = [&](int p, int idx, V v) { prow(p)[idx] = v; };
-        EI::template run_from_regs<+1, MAP_Z, MAP_MID, MAP_IO, N>(lds, twi, g, st, sa);
+        EF::template for_each_out<SL, MAP_IO>(g, mul);
+        auto st = [&](int p, int idx, V v) { out[(unsigned)(idx * P + p)] = v; };
+        EI::template run_from_regs<+1, MAP_IO, MAP_IO, MAP_PF, N>(lds, twi, g, st, sa);
     }
 };
 
 // ---------------------------------------------------------------------------
-// y_inv: ZT z-pencils of one kx; tile (z-tile bx, kx by).
+// y_inv: ZT consecutive kx pencils of one z; tile (kx-tile bx, z by).
 // ---------------------------------------------------------------------------
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struct TileYInv {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT, false, MT>;
-    static constexpr int N = P / 2;
+    static constexpr int N = P / 2, H = N + 1, HP = t4_pitch(H);
     static constexpr int LDS = E::LDS_ELEMS;
-    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t2, V* __restrict__ t1,
+    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t3, V* __restrict__ t4,
                                                const V* __restrict__ tw, V* lds, const typename E::SA& sa)
     {
-        const int z0 = bx * ZT;
-        const int kx = by;
-        const V* in = t2 + (size_t)kx * P * N + z0;
-        V* out = t1 + ((size_t)kx * N + z0) * N;
+        const int kx0 = bx * ZT;
+        const int z = by;
+        const V* in = t3 + ((size_t)kx0 * N + z) * P;  // pencil p (kx0 + p) at in + p N P
+        V* out = t4 + (size_t)z * N * HP + kx0;        // element (y, p) at out[y HP + p]
         auto ld = [&](int p, int idx) -> V {
-            return z0 + p < N ? in[(unsigned)(idx * N + p)] : V{T(0), T(0)};
+            return kx0 + p < H ? in[(unsigned)(p * N * P + idx)] : V{T(0), T(0)};
         };
         auto st = [&](int p, int idx, V v) {
-            if (z0 + p < N) out[(unsigned)(p * N + idx)] = v;
+            if (kx0 + p < H) out[(unsigned)(idx * HP + p)] = v;
         };
-        E::template run<+1, MAP_PF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
+        E::template run<+1, MAP_EF, MAP_MID, MAP_PF, P, N>(lds, tw, ld, st, sa);
     }
 };
 
@@ -193,19 +178,18 @@ template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struc
 template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXC2R {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT, false, MT>;
-    static constexpr int N = P / 2, H = N + 1;
+    static constexpr int N = P / 2, H = N + 1, HP = t4_pitch(H);
     static constexpr int XP = H + 1;  // pitch of the staged half spectra
     static constexpr int LDS = E::LDS_ELEMS > 16 * XP ? E::LDS_ELEMS : 16 * XP;
-    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t1, T* __restrict__ phi,
+    __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t4, T* __restrict__ phi,
                                                const V* __restrict__ tw, V* lds, const typename E::SA& sa)
     {
         const int y0 = bx * 16;
         const int z = by;
-        const V* t1z = t1 + (size_t)z * N + y0;
+        const V* rows = t4 + ((size_t)z * N + y0) * HP;  // 16 consecutive rows of H (pitch HP)
         for (int e = threadIdx.x; e < 16 * H; e += NT) {
-            const int row = e & 15, k = e >> 4;
-            const int y = y0 + row;
-            lds[row * XP + k] = y < N ? t1z[(unsigned)(k * N * N + row)] : V{T(0), T(0)};
+            const int row = e / H, k = e - row * H;
+            lds[row * XP + k] = y0 + row < N ? rows[(unsigned)(row * HP + k)] : V{T(0), T(0)};
         }
         __syncthreads();
         auto ld = [&](int p, int idx) -> V {
@@ -261,37 +245,37 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* __restrict__ t1, cx<T
 }
 
 template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT>
-__global__ __launch_bounds__(NT) void k_z_conv(cx<T>* __restrict__ t2, const T* __restrict__ ghat,
-                                               const cx<T>* __restrict__ twf, const cx<T>* __restrict__ twi,
-                                               const unsigned short* __restrict__ stab)
+__global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* __restrict__ t2, cx<T>* __restrict__ t3,
+                                               const T* __restrict__ ghat, const cx<T>* __restrict__ twf,
+                                               const cx<T>* __restrict__ twi, const unsigned short* __restrict__ stab)
 {
     using TL = TileZConv<T, P, FAM, B, NT, WAVE, MT>;
     __shared__ cx<T> lds[TL::LDS];
     typename TL::EF::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, t2, ghat, twf, twi, lds, sa);
+    TL::run(blockIdx.x, blockIdx.y, t2, t3, ghat, twf, twi, lds, sa);
 }
 
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
-__global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* __restrict__ t2, cx<T>* __restrict__ t1,
+__global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* __restrict__ t3, cx<T>* __restrict__ t4,
                                               const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
     using TL = TileYInv<T, P, FAM, ZT, NT, MAP_MID, MT>;
     __shared__ cx<T> lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, t2, t1, tw, lds, sa);
+    TL::run(blockIdx.x, blockIdx.y, t3, t4, tw, lds, sa);
 }
 
 template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
-__global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ t1, T* __restrict__ phi,
+__global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ t4, T* __restrict__ phi,
                                               const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
 {
     using TL = TileXC2R<T, P, FAM, NT, MAP_MID, MT>;
     __shared__ cx<T> lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, t1, phi, tw, lds, sa);
+    TL::run(blockIdx.x, blockIdx.y, t4, phi, tw, lds, sa);
 }
 
 }  // namespace ps

@@ -8,16 +8,15 @@ namespace ps {
 
 template <typename T> struct PrunedShape {
     static constexpr int ZT = sizeof(T) == 4 ? 16 : 8;  // y-pass tile: 128-byte rows of interleaved pencils
-    static constexpr int ZB = 4;                        // pencils per z-pass workgroup
+    static constexpr int ZB = ZT;                       // z pass: rows of interleaved pencils too
 };
 
 // Threads of a workgroup whose B pencils are each owned by one wavefront
 // holding >= E elements per lane (several pencils per wave for short P).
 constexpr int wave_threads(int B, int P, int E)
 {
-    int ppw = (64 * E) / P;
-    if (ppw < 1) ppw = 1;
-    if (ppw > B) ppw = B;
+    int ppw = 1;  // largest power of two dividing B with ppw P <= 64 E
+    while (ppw * 2 <= B && B % (ppw * 2) == 0 && ppw * 2 * P <= 64 * E) ppw *= 2;
     return 64 * (B / ppw);
 }
 
@@ -43,12 +42,13 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     {
         constexpr int NTZ = WAVE ? wave_threads(ZB, P, E) : threads_for(ZB, P, E);
         hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H), dim3(NTZ), 0, b.stream,
-                           static_cast<V*>(b.t2), static_cast<const T*>(b.ghat), twf, twi, b.stab);
+                           static_cast<const V*>(b.t2), static_cast<V*>(b.t3), static_cast<const T*>(b.ghat), twf, twi,
+                           b.stab);
     }
     static void y_inv(const PrunedBufs& b, const V* tw)
     {
-        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0,
-                           b.stream, static_cast<const V*>(b.t2), static_cast<V*>(b.t1), tw, b.stab);
+        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((H + ZT - 1) / ZT, N), dim3(NTY), 0,
+                           b.stream, static_cast<const V*>(b.t3), static_cast<V*>(b.t1), tw, b.stab);
     }
     static void x_c2r(const PrunedBufs& b, const V* tw)
     {

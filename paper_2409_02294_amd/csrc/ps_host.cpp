@@ -214,7 +214,7 @@ struct ps_plan_s {
     size_t split_tab = 0;                   // split-bf16 DFT-16 matrix pieces
     ps::PrunedVariant var;                  // kernel variant per pass
     size_t off_ghat = 0, ghat_bytes = 0;
-    size_t off_t1 = 0, off_t2 = 0;          // pruned intermediates
+    size_t off_t1 = 0, off_t2 = 0, off_t3 = 0;  // pruned intermediates
     size_t off_pad = 0, off_spec = 0;       // plain intermediates
     size_t off_gscr = 0;                    // kernel-build scratch (aliases intermediates)
     size_t off_batch = 0;                   // batched-solve control block (when first in a batch)
@@ -242,6 +242,7 @@ ps::PrunedBufs pruned_bufs(ps_plan p, const void* rho, void* phi, hipStream_t s)
     b.phi = phi;
     b.t1 = p->ws + p->off_t1;
     b.t2 = p->ws + p->off_t2;
+    b.t3 = p->ws + p->off_t3;
     b.ghat = p->ws + p->off_ghat;
     b.twf = p->ws + p->off_tab + p->tw_f;
     b.twi = p->ws + p->off_tab + p->tw_i;
@@ -427,9 +428,12 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
         p->off_gscr = p->off_spec;
     } else {
         p->off_t1 = off;
-        const size_t t1 = H * N * N * c, t2 = H * P * N * c;
+        const size_t hp = (H + 15) / 16 * 16;
+        const size_t t1 = std::max(H, hp) * N * N * c, t2 = H * P * N * c;
         off += align_up(t1);
         p->off_t2 = off;
+        off += align_up(t2);
+        p->off_t3 = off;
         off += align_up(t2);
         p->off_gscr = p->off_t1;
         if (p->off_gscr + gscr > off) off = align_up(p->off_gscr + gscr);
@@ -466,6 +470,7 @@ ps_status ps_plan_query(ps_plan p, ps_plan_info* info)
     if (!is_plain(p->prec)) {
         info->t1_offset = p->off_t1;
         info->t2_offset = p->off_t2;
+        info->t3_offset = p->off_t3;
         for (int k = 0; k < 5; ++k) info->variant[k] = *variant_slot(p->var, k);
         info->split_terms = p->var.mterms;
     }
@@ -548,7 +553,7 @@ ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void
     if (is_plain(p->prec)) return fail(PS_ERR_UNSUPPORTED, "debug passes exist for the pruned pipeline only");
     if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..4");
     if (!d_in || !d_out) return fail(PS_ERR_INVALID, "in and out must be non-NULL");
-    if (pass != 2 && d_in == d_out) return fail(PS_ERR_INVALID, "only pass 2 may run in place");
+    if (d_in == d_out) return fail(PS_ERR_INVALID, "passes do not run in place");
     if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
     hipStream_t st = (hipStream_t)stream;
     ps::PrunedBufs b = pruned_bufs(p, nullptr, nullptr, st);
@@ -556,16 +561,8 @@ ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void
     switch (pass) {
     case 0: b.rho = d_in; b.t1 = d_out; break;
     case 1: b.t1 = in; b.t2 = d_out; break;
-    case 2: {
-        const size_t bytes = (size_t)p->H * p->P * p->n * 2 * p->real_bytes;
-        if (d_in != d_out) {
-            hipError_t e = hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, st);
-            if (e != hipSuccess) return device_fail(e, "copy");
-        }
-        b.t2 = d_out;
-        break;
-    }
-    case 3: b.t2 = in; b.t1 = d_out; break;
+    case 2: b.t2 = in; b.t3 = d_out; break;
+    case 3: b.t3 = in; b.t1 = d_out; break;
     case 4: b.t1 = in; b.phi = d_out; break;
     }
     hipError_t e = run_pruned(p->prec, p->P, pass, pass + 1, b);
@@ -714,6 +711,7 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
             b.phi = d_phi[order[k]];
             b.t1 = p->ws + p->off_t1;
             b.t2 = p->ws + p->off_t2;
+            b.t3 = p->ws + p->off_t3;
             b.ghat = p->ws + p->off_ghat;
             b.twf = p->ws + p->off_tab + p->tw_f;
             b.twi = p->ws + p->off_tab + p->tw_i;

@@ -26,8 +26,9 @@ constexpr int NUM_ZMODES = 3;
 struct PrunedBufs {
     const void* rho;   // N^3 real
     void* phi;         // N^3 real
-    void* t1;          // [H][N][N] complex
-    void* t2;          // [H][P][N] complex
+    void* t1;          // T1 [H][N][N] complex; later T4 [N][N][HP]
+    void* t2;          // T2 [H][P][N] complex
+    void* t3;          // T3 [H][N][P] complex
     const void* ghat;  // [H][H][H] real octant, scaled
     const void* twf;   // forward-plan twiddles, family 0
     const void* twi;   // inverse-plan twiddles, family 0

@@ -52,7 +52,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("h", ctypes.c_int), ("precision", ctypes.c_int),
                 ("dx", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t), ("ghat_bytes", ctypes.c_size_t),
                 ("ready", ctypes.c_int), ("radices", ctypes.c_int * 8),
-                ("t1_offset", ctypes.c_size_t), ("t2_offset", ctypes.c_size_t), ("variant", ctypes.c_int * 5),
+                ("t1_offset", ctypes.c_size_t), ("t2_offset", ctypes.c_size_t), ("t3_offset", ctypes.c_size_t),
+                ("variant", ctypes.c_int * 5),
                 ("split_terms", ctypes.c_int)]
 
 
@@ -128,7 +129,7 @@ def ps_plan_query(plan: int) -> Dict:
     rad = [r for r in info.radices if r]
     return dict(n=info.n, p=info.p, h=info.h, precision=info.precision, dx=info.dx,
                 workspace_bytes=info.workspace_bytes, ghat_bytes=info.ghat_bytes, ready=bool(info.ready),
-                radices=rad, t1_offset=info.t1_offset, t2_offset=info.t2_offset, variant=list(info.variant), split_terms=info.split_terms)
+                radices=rad, t1_offset=info.t1_offset, t2_offset=info.t2_offset, t3_offset=info.t3_offset, variant=list(info.variant), split_terms=info.split_terms)
 
 
 def ps_green_build(plan: int, workspace: int, G: float, self_coeff: float, stream: int) -> None:

@@ -87,24 +87,26 @@ def test_passes_match_numpy(prec, n):
     a_in, t2 = run(1, a, (h, p, n), True)
     ref = np.transpose(np.fft.fft(a_in, n=p, axis=2), (0, 2, 1))
     check("y_fwd", t2, ref)
-    # pass 2: FFT along z (zero padded), product with the kernel octant, inverse, crop
+    # pass 2: FFT along z (zero padded), product with the kernel octant, inverse,
+    # crop; output T3[kx][z][ky]
     b = rng.standard_normal((h, p, n)) + 1j * rng.standard_normal((h, p, n))
-    b_in, t3 = run(2, b, (h, p, n), True)
+    b_in, t3 = run(2, b, (h, n, p), True)
     go = _ghat_octant(n, 1.0 / n)
     fold = np.minimum(np.arange(p), p - np.arange(p))
     gfull = go[:, fold, :][:, :, fold]                      # [kx][ky][kz]
     ref = np.fft.ifft(np.fft.fft(b_in, n=p, axis=2) * gfull, axis=2)[:, :, :n] * p
-    check("z_conv", t3, ref)
-    # pass 3: inverse FFT along y, crop
-    c = rng.standard_normal((h, p, n)) + 1j * rng.standard_normal((h, p, n))
-    c_in, t4 = run(3, c, (h, n, n), True)
-    ref = np.transpose(np.fft.ifft(c_in, axis=1)[:, :n, :] * p, (0, 2, 1))
-    check("y_inv", t4, ref)
-    # pass 4: inverse real FFT along x, crop
-    d = rng.standard_normal((h, n, n)) + 1j * rng.standard_normal((h, n, n))
+    check("z_conv", t3, np.transpose(ref, (0, 2, 1)))
+    # pass 3: inverse FFT along y, crop; in T3[kx][z][ky], out T4[z][y][kx] (row pitch hp)
+    hp = (h + 15) // 16 * 16
+    c = rng.standard_normal((h, n, p)) + 1j * rng.standard_normal((h, n, p))
+    c_in, t4 = run(3, c, (n, n, hp), True)
+    ref = np.transpose(np.fft.ifft(c_in, axis=2)[:, :, :n] * p, (1, 2, 0))
+    check("y_inv", t4[:, :, :h], ref)
+    # pass 4: inverse real FFT along x, crop; the row padding beyond kx = n is ignored
+    d = rng.standard_normal((n, n, hp)) + 1j * rng.standard_normal((n, n, hp))
+    d[:, :, h:] = 1e30
     d_in, out = run(4, d, (n, n, n), False)
-    spec = np.transpose(d_in, (1, 2, 0))                    # [z][y][kx]
-    ref = np.fft.irfft(spec, n=p, axis=2)[:, :, :n] * p
+    ref = np.fft.irfft(d_in[:, :, :h], n=p, axis=2)[:, :, :n] * p
     check("x_c2r", out, ref)
 
 
