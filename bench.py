@@ -132,6 +132,133 @@ def sampled_error(oracle, rho64, phi, n, ncells, seed=11):
     return float(np.abs(got - ref).max() / np.abs(ref).max()), int(ncells)
 
 
+def _graph_of(torch, fn):
+    """Capture fn() (after one eager warm-up call on the capture stream) into a
+    CUDA/HIP graph."""
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        fn()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def _time_replays(torch, g, steps, warmup):
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def batched_leg(torch, S, prec, steps, warmup):
+    """96 independent solves of sizes drawn from {32, 48, 64, 96, 128} in one
+    persistent launch, replayed from a captured graph."""
+    import numpy as np
+    from paper_2409_02294_amd import inputs
+    dens = inputs.batched_workload(96, 4000)
+    sizes = [d.shape[0] for d in dens]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    solvers = [S.Solver(n, 1.0 / n, prec) for n in sizes]
+    rhos = [torch.from_numpy(d).to("cuda", dt) for d in dens]
+    outs = [torch.empty_like(r) for r in rhos]
+    S.solve_batched(solvers, rhos, outs)  # first call: uploads the work list
+    torch.cuda.synchronize()
+    g = _graph_of(torch, lambda: S.solve_batched(solvers, rhos, outs))
+    ms = _time_replays(torch, g, steps, warmup)
+    stream = torch.cuda.current_stream().cuda_stream
+    err_flag = S.ps_batch_check(solvers[0].plan, stream)
+    # every member against the per-solve path, the smallest against the oracle
+    worst = 0.0
+    for s, r, o in zip(solvers, rhos, outs):
+        ref = s(r)
+        torch.cuda.synchronize()
+        worst = max(worst, float((o.double() - ref.double()).norm() / ref.double().norm()))
+    import oracle
+    k = int(np.argmin(sizes))
+    ref = oracle.fft_conv(rhos[k].double().cpu().numpy(), 1.0 / sizes[k])
+    oerr = oracle.rel_l2(outs[k].double().cpu().numpy(), ref)
+    rb = 8 if prec == "f64" else 4
+    b2 = sum(model_bytes(n, rb)["B2"] for n in sizes)
+    hist = {str(n): sizes.count(n) for n in sorted(set(sizes))}
+    return {"workload": "96 solves, N in {32,48,64,96,128} (seeded), 4-32 blobs each, one persistent launch per batch, "
+                        "replayed from a captured graph",
+            "precision": prec, "sizes": hist, "ms_per_batch": ms, "solves_per_s": 96.0 / (ms * 1e-3),
+            "B2_bytes_per_batch": b2, "effective_GBps_B2": b2 / (ms * 1e-3) / 1e9, "wait_error_flag": err_flag,
+            "max_rel_l2_vs_single_solves": worst, "rel_l2_vs_oracle_smallest": oerr}
+
+
+def nested_leg(torch, S, prec, nsteps, warmup):
+    """A time sequence of nested levels (384^3 coarse plus two 128^3 levels
+    refined by 2 each), blobs drifting each step; each step copies the step's
+    precomputed densities into the solver inputs and runs one batched launch.
+    The whole sequence is one captured graph; per-step latency comes from a
+    one-step graph replayed with events."""
+    import numpy as np
+    from paper_2409_02294_amd import inputs
+    geometry, sets = inputs.nested_workload(nsteps)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    solvers = [S.Solver(n, dx, prec) for (n, dx, _) in geometry]
+    dens = [[torch.empty((n, n, n), dtype=dt, device="cuda") for _ in range(nsteps)] for (n, _, _) in geometry]
+    for t, blobs in enumerate(sets):
+        for lv, (n, dx, origin) in enumerate(geometry):
+            inputs.blob_density_torch(n, blobs, dx, origin, out=dens[lv][t])
+    rin = [torch.empty((n, n, n), dtype=dt, device="cuda") for (n, _, _) in geometry]
+    outs = [torch.empty_like(r) for r in rin]
+    S.solve_batched(solvers, rin, outs)  # uploads the (fixed) work list
+    torch.cuda.synchronize()
+
+    def step(t):
+        for lv in range(len(geometry)):
+            rin[lv].copy_(dens[lv][t])
+        S.solve_batched(solvers, rin, outs)
+
+    def sequence():
+        for t in range(nsteps):
+            step(t)
+
+    gseq = _graph_of(torch, sequence)
+    ms_seq = _time_replays(torch, gseq, 1, 1)
+    gone = _graph_of(torch, lambda: S.solve_batched(solvers, rin, outs))
+    lat = []
+    for _ in range(warmup):
+        gone.replay()
+    for _ in range(nsteps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gone.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    err_flag = S.ps_batch_check(solvers[0].plan, torch.cuda.current_stream().cuda_stream)
+    # the last step's outputs against single solves of the same inputs
+    worst = 0.0
+    for s, r, o in zip(solvers, rin, outs):
+        ref = s(r)
+        torch.cuda.synchronize()
+        worst = max(worst, float((o.double() - ref.double()).norm() / ref.double().norm()))
+    rb = 8 if prec == "f64" else 4
+    b2 = sum(model_bytes(n, rb)["B2"] for (n, _, _) in geometry)
+    lat = np.array(lat)
+    return {"workload": f"{nsteps} steps of 384^3 + 2 x 128^3 nested levels (refinement 2), 32 drifting blobs, "
+                        "densities precomputed in HBM, whole sequence one captured graph",
+            "precision": prec, "steps": nsteps, "ms_per_step_sequence": ms_seq / nsteps,
+            "solves_per_s": 3 * nsteps / (ms_seq * 1e-3),
+            "step_latency_ms_p50": float(np.percentile(lat, 50)), "step_latency_ms_p99": float(np.percentile(lat, 99)),
+            "B2_bytes_per_step": b2, "effective_GBps_B2_latency_p50": b2 / (np.percentile(lat, 50) * 1e-3) / 1e9,
+            "wait_error_flag": err_flag, "max_rel_l2_vs_single_solves": worst}
+
+
 def cpu_baseline(oracle, n_target: int, n_sample: int):
     """The oracle's full FFT-convolution solve on a smaller grid, timed on
     this host, scaled to one solve of the target size by the ratio of FFT
@@ -166,6 +293,8 @@ def main() -> int:
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel variants")
     ap.add_argument("--copy-probe", action="store_true", help="also run one plain 1 GiB device copy (counter scaling)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 96-solve batched leg")
+    ap.add_argument("--nested-steps", type=int, default=200, help="steps of the nested leg (0 skips it)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -296,6 +425,16 @@ def main() -> int:
             acc[head]["rel_l2_vs_f64_path"] = float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
             acc[head]["rel_max_vs_f64_path"] = float(np.abs(a - ref).max() / np.abs(ref).max())
         out["accuracy"] = acc
+
+    side_prec = head if head in ("f32", "f64", "f32_split") else "f32"
+    if not args.no_batched:
+        log("batched leg")
+        out["batched"] = batched_leg(torch, S, side_prec, max(5, args.steps), args.warmup)
+        torch.cuda.empty_cache()
+    if args.nested_steps > 0:
+        log("nested leg")
+        out["nested"] = nested_leg(torch, S, side_prec, args.nested_steps, args.warmup)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         import oracle

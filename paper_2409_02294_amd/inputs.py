@@ -145,6 +145,38 @@ def batched_workload(count: int = 96, seed: int = 4000,
     return out
 
 
+def blob_density_torch(n: int, blobs: BlobSet, dx: float | None = None,
+                       origin: Sequence[float] = (0.0, 0.0, 0.0), cutoff: float = 7.0,
+                       out=None, device="cuda"):
+    """:func:`blob_density` evaluated with torch on ``device`` in float64 (same
+    formula, cell ranges and truncation), for workloads too large to build on
+    the host; ``out`` (a float32 or float64 tensor) receives the result."""
+    import torch
+    if dx is None:
+        dx = 1.0 / n
+    rho = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    ox, oy, oz = (float(o) for o in origin)
+    for (cx, cy, cz), s, m in zip(blobs.centres, blobs.sigmas, blobs.masses):
+        amp = m / ((2.0 * math.pi) ** 1.5 * s ** 3)
+        sl, prof = [], []
+        for c, o in ((cz, oz), (cy, oy), (cx, ox)):
+            lo = max(0, int(math.floor((c - cutoff * s - o) / dx - 0.5)))
+            hi = min(n, int(math.ceil((c + cutoff * s - o) / dx - 0.5)) + 1)
+            if hi <= lo:
+                break
+            xs = o + (torch.arange(lo, hi, dtype=torch.float64, device=device) + 0.5) * dx
+            sl.append(slice(lo, hi))
+            prof.append(torch.exp(-((xs - c) ** 2) / (2.0 * s * s)))
+        if len(sl) != 3:
+            continue
+        ez, ey, ex = prof
+        rho[sl[0], sl[1], sl[2]] += amp * (ez[:, None, None] * (ey[None, :, None] * ex[None, None, :]))
+    if out is not None:
+        out.copy_(rho)
+        return out
+    return rho
+
+
 def nested_workload(steps: int, coarse_n: int = 384, fine_n: int = 128, levels: int = 2,
                     nblobs: int = 32, seed: int = 5000, vmax: float = 1e-3):
     """Blob parameters and level geometry for a drifting-blob time sequence.
