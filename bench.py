@@ -161,8 +161,8 @@ def _time_replays(torch, g, steps, warmup):
 
 
 def batched_leg(torch, S, prec, steps, warmup):
-    """96 independent solves of sizes drawn from {32, 48, 64, 96, 128} in one
-    persistent launch, replayed from a captured graph."""
+    """96 independent solves of sizes drawn from {32, 48, 64, 96, 128} as one
+    batched solve (five grouped launches), replayed from a captured graph."""
     import numpy as np
     from paper_2409_02294_amd import inputs
     dens = inputs.batched_workload(96, 4000)
@@ -175,8 +175,6 @@ def batched_leg(torch, S, prec, steps, warmup):
     torch.cuda.synchronize()
     g = _graph_of(torch, lambda: S.solve_batched(solvers, rhos, outs))
     ms = _time_replays(torch, g, steps, warmup)
-    stream = torch.cuda.current_stream().cuda_stream
-    err_flag = S.ps_batch_check(solvers[0].plan, stream)
     # every member against the per-solve path, the smallest against the oracle
     worst = 0.0
     for s, r, o in zip(solvers, rhos, outs):
@@ -190,10 +188,10 @@ def batched_leg(torch, S, prec, steps, warmup):
     rb = 8 if prec == "f64" else 4
     b2 = sum(model_bytes(n, rb)["B2"] for n in sizes)
     hist = {str(n): sizes.count(n) for n in sorted(set(sizes))}
-    return {"workload": "96 solves, N in {32,48,64,96,128} (seeded), 4-32 blobs each, one persistent launch per batch, "
+    return {"workload": "96 solves, N in {32,48,64,96,128} (seeded), 4-32 blobs each, one batched solve (5 grouped launches), "
                         "replayed from a captured graph",
             "precision": prec, "sizes": hist, "ms_per_batch": ms, "solves_per_s": 96.0 / (ms * 1e-3),
-            "B2_bytes_per_batch": b2, "effective_GBps_B2": b2 / (ms * 1e-3) / 1e9, "wait_error_flag": err_flag,
+            "B2_bytes_per_batch": b2, "effective_GBps_B2": b2 / (ms * 1e-3) / 1e9,
             "max_rel_l2_vs_single_solves": worst, "rel_l2_vs_oracle_smallest": oerr}
 
 
@@ -240,7 +238,6 @@ def nested_leg(torch, S, prec, nsteps, warmup):
         e1.record()
         torch.cuda.synchronize()
         lat.append(e0.elapsed_time(e1))
-    err_flag = S.ps_batch_check(solvers[0].plan, torch.cuda.current_stream().cuda_stream)
     # the last step's outputs against single solves of the same inputs
     worst = 0.0
     for s, r, o in zip(solvers, rin, outs):
@@ -256,7 +253,7 @@ def nested_leg(torch, S, prec, nsteps, warmup):
             "solves_per_s": 3 * nsteps / (ms_seq * 1e-3),
             "step_latency_ms_p50": float(np.percentile(lat, 50)), "step_latency_ms_p99": float(np.percentile(lat, 99)),
             "B2_bytes_per_step": b2, "effective_GBps_B2_latency_p50": b2 / (np.percentile(lat, 50) * 1e-3) / 1e9,
-            "wait_error_flag": err_flag, "max_rel_l2_vs_single_solves": worst}
+            "max_rel_l2_vs_single_solves": worst}
 
 
 def cpu_baseline(oracle, n_target: int, n_sample: int):
@@ -281,6 +278,96 @@ def cpu_baseline(oracle, n_target: int, n_sample: int):
     }
 
 
+COPY_ELEMS = 1 << 28  # float32 elements of the counter-scaling copy (1 GiB read, 1 GiB written)
+
+
+def pass_loop(torch, S, args) -> int:
+    """Each pass of one solve (its own workspace buffers, fixed variants)
+    args.pass_loop times, then a plain elementwise copy of COPY_ELEMS floats
+    as many times; nothing is timed.  Run under rocprofv3 --pmc."""
+    n, prec = args.n, args.precision
+    s = S.Solver(n, 1.0 / n, prec)
+    if args.variants:
+        for k, v in enumerate(int(x) for x in args.variants.split(",")):
+            S.ps_plan_set_variant(s.plan, k, v)
+    info = s.info()
+    ws = s.workspace.data_ptr()
+    t1, t2, t3 = ws + info["t1_offset"], ws + info["t2_offset"], ws + info["t3_offset"]
+    dt = torch.float64 if prec.startswith("f64") else torch.float32
+    rho = torch.rand((n, n, n), dtype=dt, device="cuda")
+    phi = torch.empty_like(rho)
+    io = [(rho.data_ptr(), t1), (t1, t2), (t2, t3), (t3, t1), (t1, phi.data_ptr())]
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(args.pass_loop):
+        for k in range(5):
+            S.ps_debug_pass(s.plan, k, io[k][0], io[k][1], stream)
+    torch.cuda.synchronize()
+    del rho, phi, s
+    torch.cuda.empty_cache()
+    a = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.pass_loop):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"pass_loop": args.pass_loop, "n": n, "precision": prec, "variants": info["variant"]
+                      if not args.variants else [int(x) for x in args.variants.split(",")]}), flush=True)
+    return 0
+
+
+def _counter_rows(path):
+    """{dispatch id: (kernel name, summed counter value)} from a rocprofv3 counter CSV."""
+    import csv
+    rows = {}
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            d = int(r["Dispatch_Id"])
+            name, val = r["Kernel_Name"], float(r["Counter_Value"])
+            prev = rows.get(d, (name, 0.0))
+            rows[d] = (name, prev[1] + val)
+    return rows
+
+
+def ingest_counters(args) -> int:
+    """Average FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per pass kernel of
+    a --pass-loop run, scaled by what the same counters read for the 1 GiB
+    elementwise copy, into profiles/hbm_traffic_counters.json."""
+    keys = {"k_x_r2c": "x_r2c", "k_y_fwd": "y_fwd", "k_z_conv": "z_conv", "k_y_inv": "y_inv", "k_x_c2r": "x_c2r"}
+    avg = {}
+    for which, path in zip(("fetch", "write"), args.ingest_counters):
+        acc = {}
+        for name, val in _counter_rows(path).values():
+            key = next((v for k, v in keys.items() if k in name), "copy" if "neg" in name else None)
+            if key is not None:
+                acc.setdefault(key, []).append(val)
+        avg[which] = {k: sum(v) / len(v) for k, v in acc.items()}
+    copy_kib = COPY_ELEMS * 4 / 1024.0
+    fac = {w: copy_kib / avg[w]["copy"] for w in ("fetch", "write")}
+    rb = 8 if args.precision.startswith("f64") else 4
+    pb = pass_bytes(args.n, rb)
+    out_path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.json")
+    doc = {"about": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each "
+                    "scaled by the factor that makes a 1 GiB elementwise copy read and write 1 GiB",
+           "copy_KiB_expected": copy_kib, "copy_KiB_read": {w: avg[w]["copy"] for w in avg}, "factor": fac,
+           "kernels": {}}
+    if os.path.exists(out_path):
+        with open(out_path) as fh:
+            doc["kernels"] = json.load(fh).get("kernels", {})
+    for k in PASS_NAMES:
+        if k not in avg["fetch"] or k not in avg["write"]:
+            continue
+        f, w = avg["fetch"][k] * fac["fetch"], avg["write"][k] * fac["write"]
+        doc["kernels"][f"{k}/n{args.n}/{args.precision}"] = {
+            "fetch_KiB_raw": avg["fetch"][k], "write_KiB_raw": avg["write"][k],
+            "bytes_per_launch": (f + w) * 1024.0, "read_bytes": f * 1024.0, "write_bytes": w * 1024.0,
+            "algorithmic_bytes": pb[k], "ratio_to_algorithmic": (f + w) * 1024.0 / pb[k],
+            "source_hash": source_hash(),
+        }
+    with open(out_path, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(json.dumps(doc["kernels"], indent=1))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,11 +379,19 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel variants")
-    ap.add_argument("--copy-probe", action="store_true", help="also run one plain 1 GiB device copy (counter scaling)")
+    ap.add_argument("--pass-loop", type=int, default=0, metavar="K",
+                    help="instead of the benchmark: run each pass of one solve K times, then a 1 GiB "
+                         "elementwise copy K times (the target of the HBM counter runs)")
+    ap.add_argument("--variants", default="", help="kernel variants per pass for --pass-loop, e.g. 0,1,2,0,0")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs of a --pass-loop run into "
+                         "profiles/hbm_traffic_counters.json")
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-solve batched leg")
     ap.add_argument("--nested-steps", type=int, default=200, help="steps of the nested leg (0 skips it)")
     args = ap.parse_args()
 
+    if args.ingest_counters:
+        return ingest_counters(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -311,6 +406,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     n = args.n
+    if args.pass_loop:
+        return pass_loop(torch, S, args)
     name = {512: "blobs512", 256: "blobs256", 32: "blobs32"}.get(n)
     t0 = time.perf_counter()
     log(f"generating the {n}^3 density")
@@ -351,13 +448,6 @@ def main() -> int:
         log(f"{prec}: {rec['ms_per_solve']:.3f} ms/solve")
         del s, rho, phi
         torch.cuda.empty_cache()
-
-    if args.copy_probe:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     hr = results[head]
     if "error" in hr:

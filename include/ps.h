@@ -108,25 +108,21 @@ ps_status ps_green_build(ps_plan p, void *d_workspace, double G, double self_coe
 /* One solve: phi = potential of rho, enqueued on `stream`. */
 ps_status ps_solve(ps_plan p, const void *d_rho, void *d_phi, void *stream);
 
-/* count (1..1024) independent solves in one persistent launch on `stream`
- * (after a small kernel that clears its counters).  Plans may differ in n
- * but must share one pruned precision (PS_F64, PS_F32 or PS_F32_SPLIT with
- * six product terms); each plan appears at most once and must be built;
- * rho[i] and phi[i] follow the layout of ps_solve, and no output may overlap
- * another array of the batch.  Work is handed out to workgroups in pass-major
- * order with the largest solves first; a tile waits (bounded) until the
- * previous pass of its solve has finished.  The first call with a given list
- * of plans and arrays uploads a small work list into plans[0]'s workspace
- * and so must not be under stream capture (PS_ERR_CAPTURE); later calls with
- * the same list upload nothing and can be captured into a HIP graph.  The
- * same plan must not lead two batches in flight at once. */
+/* count (1..1024) independent solves enqueued on `stream`.  Members are
+ * grouped by length and kernel variant; each pass is one launch per group,
+ * over the group's members (grid z), with the same kernels ps_solve uses, so
+ * a member's result equals ps_solve's for its plan bitwise.  All plans must
+ * share one pruned precision (PS_F64, PS_F32 or PS_F32_SPLIT); each plan
+ * appears at most once and must be built; rho[i] and phi[i] follow the
+ * layout of ps_solve, and no output may overlap another array of the batch.
+ * The first call with a given list of plans, arrays and kernel variants
+ * uploads the members' buffer records into plans[0]'s workspace and
+ * synchronises `stream`, so it must not be under stream capture
+ * (PS_ERR_CAPTURE); later calls with the same list upload nothing, do not
+ * synchronise and can be captured into a HIP graph.  The same plan must not
+ * lead two batches in flight at once. */
 ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d_rho, void *const *d_phi,
                            void *stream);
-
-/* Synchronise `stream` and report whether the last batch led by `first`
- * (its plans[0]) gave up a dependency wait (*error = 1; its results are then
- * invalid) or not (*error = 0). */
-ps_status ps_batch_check(ps_plan first, void *stream, int *error);
 
 /* Choose the kernel variant of one pass of a pruned plan (host only, no HIP
  * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = radix-32-

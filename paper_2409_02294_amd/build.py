@@ -39,7 +39,9 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, "-x", "hip", *COMMON, "-c", src, "-o", obj]
+    # .cpp sources hold host code only (the ABI layer): no device pass
+    host_only = ["--offload-host-only"] if src.endswith(".cpp") else []
+    cmd = [HIPCC, "-x", "hip", *COMMON, *host_only, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -28,6 +28,7 @@
 // G dx^3 / P^3, so the pipeline itself applies no normalisation.
 #pragma once
 #include "plans.hpp"
+#include "solve_rec.hpp"
 
 namespace ps {
 
@@ -37,8 +38,7 @@ __host__ __device__ constexpr int t4_pitch(int H) { return (H + 15) / 16 * 16; }
 
 // Each pass is a tile function (one workgroup's share, addressed by tile
 // coordinates, using a caller-provided LDS buffer of at least LDS elements),
-// wrapped below as a one-tile-per-workgroup kernel; the persistent batched
-// kernel calls the same tile functions.
+// wrapped below as a one-tile-per-workgroup kernel.
 
 // ---------------------------------------------------------------------------
 // x_r2c: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
@@ -220,62 +220,95 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXC
 };
 
 // ---------------------------------------------------------------------------
-// One-tile-per-workgroup kernels.
+// One-tile-per-workgroup kernels.  Grid (x, y) are tile coordinates; grid z
+// selects the solve's record in `list`.  A non-NULL `in` or `out` replaces the
+// pass's input or output array of the record (a single solve's rho and phi).
 // ---------------------------------------------------------------------------
+template <typename X> __device__ __forceinline__ X* gp(const PS_GLOBAL void* p)
+{
+    return (X*)(const PS_GLOBAL X*)p;
+}
+template <typename X> __device__ __forceinline__ X* gp(PS_GLOBAL void* p)
+{
+    return (X*)(PS_GLOBAL X*)p;
+}
+template <typename V, int FAM> __device__ __forceinline__ const V* tw_fwd(const SolveRec& s)
+{
+    return gp<const V>(FAM == 1 ? s.twf1 : s.twf);
+}
+template <typename V, int FAM> __device__ __forceinline__ const V* tw_inv(const SolveRec& s)
+{
+    return gp<const V>(FAM == 1 ? s.twi1 : s.twi);
+}
+
 template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
-__global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ rho, cx<T>* __restrict__ t1,
-                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
+__global__ __launch_bounds__(NT) void k_x_r2c(const T* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                              const unsigned short* __restrict__ stab)
 {
     using TL = TileXR2C<T, P, FAM, NT, MAP_MID, MT>;
-    __shared__ cx<T> lds[TL::LDS];
+    using V = cx<T>;
+    __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, rho, t1, tw, lds, sa);
+    const SolveRec& s = list[blockIdx.z];
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const T>(s.rho), out ? out : gp<V>(s.t1), tw_fwd<V, FAM>(s), lds,
+            sa);
 }
 
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
-__global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* __restrict__ t1, cx<T>* __restrict__ t2,
-                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
+__global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                              const unsigned short* __restrict__ stab)
 {
     using TL = TileYFwd<T, P, FAM, ZT, NT, MAP_MID, MT>;
-    __shared__ cx<T> lds[TL::LDS];
+    using V = cx<T>;
+    __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, t1, t2, tw, lds, sa);
+    const SolveRec& s = list[blockIdx.z];
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t1), out ? out : gp<V>(s.t2), tw_fwd<V, FAM>(s), lds,
+            sa);
 }
 
 template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT>
-__global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* __restrict__ t2, cx<T>* __restrict__ t3,
-                                               const T* __restrict__ ghat, const cx<T>* __restrict__ twf,
-                                               const cx<T>* __restrict__ twi, const unsigned short* __restrict__ stab)
+__global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                               const unsigned short* __restrict__ stab)
 {
     using TL = TileZConv<T, P, FAM, B, NT, WAVE, MT>;
-    __shared__ cx<T> lds[TL::LDS];
+    using V = cx<T>;
+    __shared__ V lds[TL::LDS];
     typename TL::EF::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, t2, t3, ghat, twf, twi, lds, sa);
+    const SolveRec& s = list[blockIdx.z];
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t2), out ? out : gp<V>(s.t3), gp<const T>(s.ghat),
+            tw_fwd<V, FAM>(s), tw_inv<V, FAM>(s), lds, sa);
 }
 
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
-__global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* __restrict__ t3, cx<T>* __restrict__ t4,
-                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
+__global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                              const unsigned short* __restrict__ stab)
 {
     using TL = TileYInv<T, P, FAM, ZT, NT, MAP_MID, MT>;
-    __shared__ cx<T> lds[TL::LDS];
+    using V = cx<T>;
+    __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, t3, t4, tw, lds, sa);
+    const SolveRec& s = list[blockIdx.z];
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t3), out ? out : gp<V>(s.t1), tw_inv<V, FAM>(s), lds,
+            sa);
 }
 
 template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
-__global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ t4, T* __restrict__ phi,
-                                              const cx<T>* __restrict__ tw, const unsigned short* __restrict__ stab)
+__global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* in, T* out, const SolveRec* __restrict__ list,
+                                              const unsigned short* __restrict__ stab)
 {
     using TL = TileXC2R<T, P, FAM, NT, MAP_MID, MT>;
-    __shared__ cx<T> lds[TL::LDS];
+    using V = cx<T>;
+    __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
-    TL::run(blockIdx.x, blockIdx.y, t4, phi, tw, lds, sa);
+    const SolveRec& s = list[blockIdx.z];
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t1), out ? out : gp<T>(s.phi), tw_inv<V, FAM>(s), lds,
+            sa);
 }
 
 }  // namespace ps

@@ -28,69 +28,63 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     static constexpr int NTX = threads_for(8, P, E);
     static constexpr int NTY = threads_for(ZT, P, E);
 
-    static void x_r2c(const PrunedBufs& b, const V* tw)
+    static void x_r2c(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
-                           static_cast<const T*>(b.rho), static_cast<V*>(b.t1), tw, b.stab);
+        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N, b.count), dim3(NTX), 0,
+                           b.stream, static_cast<const T*>(b.in[0]), static_cast<V*>(b.out[0]), b.list, b.stab);
     }
-    static void y_fwd(const PrunedBufs& b, const V* tw)
+    static void y_fwd(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((N + ZT - 1) / ZT, H), dim3(NTY), 0,
-                           b.stream, static_cast<const V*>(b.t1), static_cast<V*>(b.t2), tw, b.stab);
+        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((N + ZT - 1) / ZT, H, b.count), dim3(NTY),
+                           0, b.stream, static_cast<const V*>(b.in[1]), static_cast<V*>(b.out[1]), b.list, b.stab);
     }
-    template <bool WAVE> static void z_conv(const PrunedBufs& b, const V* twf, const V* twi)
+    template <bool WAVE> static void z_conv(const PrunedBufs& b)
     {
         constexpr int NTZ = WAVE ? wave_threads(ZB, P, E) : threads_for(ZB, P, E);
-        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H), dim3(NTZ), 0, b.stream,
-                           static_cast<const V*>(b.t2), static_cast<V*>(b.t3), static_cast<const T*>(b.ghat), twf, twi,
-                           b.stab);
+        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H, b.count), dim3(NTZ), 0, b.stream,
+                           static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab);
     }
-    static void y_inv(const PrunedBufs& b, const V* tw)
+    static void y_inv(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((H + ZT - 1) / ZT, N), dim3(NTY), 0,
-                           b.stream, static_cast<const V*>(b.t3), static_cast<V*>(b.t1), tw, b.stab);
+        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((H + ZT - 1) / ZT, N, b.count), dim3(NTY),
+                           0, b.stream, static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab);
     }
-    static void x_c2r(const PrunedBufs& b, const V* tw)
+    static void x_c2r(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N), dim3(NTX), 0, b.stream,
-                           static_cast<const V*>(b.t1), static_cast<T*>(b.phi), tw, b.stab);
+        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N, b.count), dim3(NTX), 0,
+                           b.stream, static_cast<const V*>(b.in[4]), static_cast<T*>(b.out[4]), b.list, b.stab);
     }
 };
 
 // Split matrix-core plans keep the radix-16 family (family 1 has no radix-16 stage).
 template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int hi, const PrunedBufs& b)
 {
-    using V = cx<T>;
     using L0 = PassLaunch<T, P, 0, MT>;
     constexpr bool F1 = has_fam1<P>() && MT == 0;
     using L1 = PassLaunch<T, P, F1 ? 1 : 0, MT>;
-    const V* twf0 = static_cast<const V*>(b.twf);
-    const V* twi0 = static_cast<const V*>(b.twi);
-    const V* twf1 = static_cast<const V*>(F1 ? b.twf1 : b.twf);
-    const V* twi1 = static_cast<const V*>(F1 ? b.twi1 : b.twi);
     const PrunedVariant& v = b.var;
     for (int pass = lo; pass < hi; ++pass) {
         switch (pass) {
         case 0:
-            if (v.x_fam == 1 && F1) L1::x_r2c(b, twf1);
-            else L0::x_r2c(b, twf0);
+            if (v.x_fam == 1 && F1) L1::x_r2c(b);
+            else L0::x_r2c(b);
             break;
         case 1:
-            if (v.y_fam == 1 && F1) L1::y_fwd(b, twf1);
-            else L0::y_fwd(b, twf0);
+            if (v.y_fam == 1 && F1) L1::y_fwd(b);
+            else L0::y_fwd(b);
             break;
         case 2:
-            if (v.zmode == 2 && F1) L1::template z_conv<true>(b, twf1, twi1);
-            else if (v.zmode >= 1) L0::template z_conv<true>(b, twf0, twi0);
-            else L0::template z_conv<false>(b, twf0, twi0);
+            if (v.zmode == 2 && F1) L1::template z_conv<true>(b);
+            else if (v.zmode >= 1) L0::template z_conv<true>(b);
+            else L0::template z_conv<false>(b);
             break;
         case 3:
-            if (v.yi_fam == 1 && F1) L1::y_inv(b, twi1);
-            else L0::y_inv(b, twi0);
+            if (v.yi_fam == 1 && F1) L1::y_inv(b);
+            else L0::y_inv(b);
             break;
         case 4:
-            if (v.xc_fam == 1 && F1) L1::x_c2r(b, twi1);
-            else L0::x_c2r(b, twi0);
+            if (v.xc_fam == 1 && F1) L1::x_c2r(b);
+            else L0::x_c2r(b);
             break;
         default:
             return hipErrorInvalidValue;

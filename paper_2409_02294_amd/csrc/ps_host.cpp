@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -18,7 +19,6 @@
 #include <string>
 #include <vector>
 
-#include "batch_types.hpp"
 #include "ps_internal.hpp"
 
 namespace {
@@ -40,26 +40,9 @@ ps_status device_fail(hipError_t e, const char* where)
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-// Batched-solve control block kept in the workspace of a batch's first plan.
+// Solve records of a batch, kept in the workspace of the batch's first plan.
 constexpr int MAX_BATCH = 1024;
-struct BatchLayout {
-    size_t ctl, sol, prefix, done, bytes;
-};
-BatchLayout batch_layout(int ns)
-{
-    BatchLayout L;
-    size_t o = 0;
-    L.ctl = o;
-    o += align_up(sizeof(ps::BatchCtl));
-    L.sol = o;
-    o += align_up((size_t)ns * sizeof(ps::BatchSolve));
-    L.prefix = o;
-    o += align_up((size_t)5 * (ns + 1) * sizeof(int));
-    L.done = o;
-    o += align_up((size_t)ns * 5 * sizeof(unsigned));
-    L.bytes = o;
-    return L;
-}
+size_t batch_bytes(int ns) { return align_up((size_t)ns * sizeof(ps::SolveRec)); }
 
 bool is_plain(ps_precision p) { return p == PS_F64_PLAIN || p == PS_F32_PLAIN; }
 bool is_f64(ps_precision p) { return p == PS_F64 || p == PS_F64_PLAIN; }
@@ -217,10 +200,10 @@ struct ps_plan_s {
     size_t off_t1 = 0, off_t2 = 0, off_t3 = 0;  // pruned intermediates
     size_t off_pad = 0, off_spec = 0;       // plain intermediates
     size_t off_gscr = 0;                    // kernel-build scratch (aliases intermediates)
-    size_t off_batch = 0;                   // batched-solve control block (when first in a batch)
+    size_t off_rec = 0;                     // this plan's own solve record (pruned plans)
+    size_t off_batch = 0;                   // solve records of a batch this plan leads
     size_t ws_bytes = 0;
-    std::vector<uintptr_t> batch_sig;       // batch whose work list is in the workspace
-    std::vector<unsigned char> batch_blob;  // host copy of that work list
+    std::vector<uintptr_t> batch_sig;       // batch whose records are in the workspace
     // bound state
     unsigned char* ws = nullptr;
     bool ready = false;
@@ -235,19 +218,31 @@ ps_status check_plan(ps_plan p)
     return PS_OK;
 }
 
+ps::SolveRec solve_rec(ps_plan p, const void* rho, void* phi)
+{
+    ps::SolveRec r;
+    r.rho = rho;
+    r.phi = phi;
+    r.t1 = p->ws + p->off_t1;
+    r.t2 = p->ws + p->off_t2;
+    r.t3 = p->ws + p->off_t3;
+    r.ghat = p->ws + p->off_ghat;
+    r.twf = p->ws + p->off_tab + p->tw_f;
+    r.twi = p->ws + p->off_tab + p->tw_i;
+    r.twf1 = p->ws + p->off_tab + p->tw_f1;
+    r.twi1 = p->ws + p->off_tab + p->tw_i1;
+    return r;
+}
+
+// One solve with the plan's own record; rho and phi replace the input of
+// pass 0 and the output of pass 4.
 ps::PrunedBufs pruned_bufs(ps_plan p, const void* rho, void* phi, hipStream_t s)
 {
     ps::PrunedBufs b;
-    b.rho = rho;
-    b.phi = phi;
-    b.t1 = p->ws + p->off_t1;
-    b.t2 = p->ws + p->off_t2;
-    b.t3 = p->ws + p->off_t3;
-    b.ghat = p->ws + p->off_ghat;
-    b.twf = p->ws + p->off_tab + p->tw_f;
-    b.twi = p->ws + p->off_tab + p->tw_i;
-    b.twf1 = p->ws + p->off_tab + p->tw_f1;
-    b.twi1 = p->ws + p->off_tab + p->tw_i1;
+    b.list = reinterpret_cast<const ps::SolveRec*>(p->ws + p->off_rec);
+    b.count = 1;
+    b.in[0] = rho;
+    b.out[4] = phi;
     b.stab = reinterpret_cast<const unsigned short*>(p->ws + p->off_tab + p->split_tab);
     b.var = p->var;
     b.stream = s;
@@ -437,8 +432,10 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
         off += align_up(t2);
         p->off_gscr = p->off_t1;
         if (p->off_gscr + gscr > off) off = align_up(p->off_gscr + gscr);
+        p->off_rec = off;
+        off += align_up(sizeof(ps::SolveRec));
         p->off_batch = off;
-        off += batch_layout(MAX_BATCH).bytes;
+        off += batch_bytes(MAX_BATCH);
     }
     p->ws_bytes = off;
     *out = p;
@@ -507,9 +504,15 @@ ps_status ps_green_build(ps_plan p, void* d_workspace, double G, double self_coe
     gb.stream = st;
     e = ps::green_run(p->P, gb);
     if (e != hipSuccess) return device_fail(e, "kernel build launch");
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return device_fail(e, "kernel build");
     p->ws = ws;
+    ps::SolveRec rec{};
+    if (!is_plain(p->prec)) {
+        rec = solve_rec(p, nullptr, nullptr);
+        e = hipMemcpyAsync(ws + p->off_rec, &rec, sizeof(rec), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return device_fail(e, "solve record upload");
+    }
+    e = hipStreamSynchronize(st);  // also ends the uploads from host memory
+    if (e != hipSuccess) return device_fail(e, "kernel build");
     p->G = G;
     p->self_coeff = self_coeff;
     p->ready = true;
@@ -557,14 +560,8 @@ ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void
     if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
     hipStream_t st = (hipStream_t)stream;
     ps::PrunedBufs b = pruned_bufs(p, nullptr, nullptr, st);
-    void* in = const_cast<void*>(d_in);
-    switch (pass) {
-    case 0: b.rho = d_in; b.t1 = d_out; break;
-    case 1: b.t1 = in; b.t2 = d_out; break;
-    case 2: b.t2 = in; b.t3 = d_out; break;
-    case 3: b.t3 = in; b.t1 = d_out; break;
-    case 4: b.t1 = in; b.phi = d_out; break;
-    }
+    b.in[pass] = d_in;
+    b.out[pass] = d_out;
     hipError_t e = run_pruned(p->prec, p->P, pass, pass + 1, b);
     if (e != hipSuccess) return device_fail(e, "pass launch");
     return PS_OK;
@@ -653,14 +650,10 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
         if (!plans[i]) return fail(PS_ERR_INVALID, "plan " + std::to_string(i) + " is NULL");
     const ps_precision prec = plans[0]->prec;
     if (is_plain(prec)) return fail(PS_ERR_UNSUPPORTED, "batched solves use the pruned pipeline");
-    const int mterms = plans[0]->var.mterms;
-    if (prec == PS_F32_SPLIT && mterms != 6)
-        return fail(PS_ERR_UNSUPPORTED, "batched split solves use the six-term product");
     for (int i = 0; i < count; ++i) {
         const ps_plan p = plans[i];
         const std::string who = "solve " + std::to_string(i);
-        if (p->prec != prec || p->var.mterms != mterms)
-            return fail(PS_ERR_INVALID, who + ": all plans of a batch need the same precision");
+        if (p->prec != prec) return fail(PS_ERR_INVALID, who + ": all plans of a batch need the same precision");
         if (!d_rho[i] || !d_phi[i]) return fail(PS_ERR_INVALID, who + ": rho and phi must be non-NULL");
         if ((uintptr_t)d_rho[i] % p->real_bytes || (uintptr_t)d_phi[i] % p->real_bytes)
             return fail(PS_ERR_INVALID, who + ": rho and phi must be aligned to their element size");
@@ -681,90 +674,59 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
         if (!plans[i]->ready) return fail(PS_ERR_NOT_READY, "solve " + std::to_string(i) + ": call ps_green_build first");
     hipStream_t st = (hipStream_t)stream;
     ps_plan head = plans[0];
-    const BatchLayout L = batch_layout(count);
-    // the work list: solves largest first, pass-major items
+    // Members sorted by length (largest first), then by kernel variants, so
+    // that per pass every run of equal-length members with the same kernel
+    // is one launch over their adjacent records.
+    auto vkey = [&](int i) {
+        const ps::PrunedVariant& v = plans[i]->var;
+        return std::array<int, 7>{-plans[i]->P, v.x_fam, v.y_fam, v.zmode, v.yi_fam, v.xc_fam, v.mterms};
+    };
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return vkey(a) < vkey(b); });
     std::vector<uintptr_t> sig;
     sig.push_back((uintptr_t)count);
-    for (int i = 0; i < count; ++i) {
+    for (int k = 0; k < count; ++k) {
+        const int i = order[k];
         sig.push_back((uintptr_t)plans[i]);
         sig.push_back((uintptr_t)d_rho[i]);
         sig.push_back((uintptr_t)d_phi[i]);
         sig.push_back((uintptr_t)plans[i]->ws);
+        for (int x : vkey(i)) sig.push_back((uintptr_t)(intptr_t)x);
     }
+    auto* dlist = reinterpret_cast<ps::SolveRec*>(head->ws + head->off_batch);
     if (sig != head->batch_sig) {
         bool cap = false;
         hipError_t e;
         if (!capturing(st, cap, e)) return device_fail(e, "hipStreamIsCapturing");
-        if (cap) return fail(PS_ERR_CAPTURE, "the first call with a new batch uploads its work list; not under capture");
-        std::vector<int> order(count);
-        for (int i = 0; i < count; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plans[a]->P > plans[b]->P; });
-        std::vector<unsigned char> blob(L.bytes, 0);
-        auto* ctl = reinterpret_cast<ps::BatchCtl*>(blob.data() + L.ctl);
-        auto* sol = reinterpret_cast<ps::BatchSolve*>(blob.data() + L.sol);
-        auto* prefix = reinterpret_cast<int*>(blob.data() + L.prefix);
-        int pass_total[5] = {0, 0, 0, 0, 0};
-        for (int k = 0; k < count; ++k) {
-            const ps_plan p = plans[order[k]];
-            ps::BatchSolve& b = sol[k];
-            b.rho = d_rho[order[k]];
-            b.phi = d_phi[order[k]];
-            b.t1 = p->ws + p->off_t1;
-            b.t2 = p->ws + p->off_t2;
-            b.t3 = p->ws + p->off_t3;
-            b.ghat = p->ws + p->off_ghat;
-            b.twf = p->ws + p->off_tab + p->tw_f;
-            b.twi = p->ws + p->off_tab + p->tw_i;
-            b.P = p->P;
-            ps::batch_tiles(p->P, (int)p->real_bytes, b.ntile);
-            for (int ph = 0; ph < 5; ++ph) {
-                prefix[ph * (count + 1) + k] = pass_total[ph];
-                pass_total[ph] += b.ntile[ph];
-            }
-        }
-        for (int ph = 0; ph < 5; ++ph) prefix[ph * (count + 1) + count] = pass_total[ph];
-        ctl->nsolves = count;
-        ctl->pass_begin[0] = 0;
-        for (int ph = 0; ph < 5; ++ph) ctl->pass_begin[ph + 1] = ctl->pass_begin[ph] + pass_total[ph];
-        ctl->total = ctl->pass_begin[5];
-        head->batch_blob.swap(blob);
-        e = hipMemcpyAsync(head->ws + head->off_batch, head->batch_blob.data(), L.bytes, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return device_fail(e, "work list upload");
+        if (cap) return fail(PS_ERR_CAPTURE, "the first call with a new batch uploads its records; not under capture");
+        std::vector<ps::SolveRec> recs(count);
+        for (int k = 0; k < count; ++k) recs[k] = solve_rec(plans[order[k]], d_rho[order[k]], d_phi[order[k]]);
+        e = hipMemcpyAsync(dlist, recs.data(), recs.size() * sizeof(ps::SolveRec), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host array is released on return
+        if (e != hipSuccess) return device_fail(e, "batch record upload");
         head->batch_sig = sig;
     }
-    const auto* ctl = reinterpret_cast<const ps::BatchCtl*>(head->batch_blob.data() + L.ctl);
-    int pmax = 0;
-    for (int i = 0; i < count; ++i) pmax = std::max(pmax, plans[i]->P);
-    ps::BatchArgs a;
-    a.kind = prec == PS_F64 ? 2 : (prec == PS_F32_SPLIT ? 1 : 0);
-    a.pmax = pmax;
-    a.ctl = reinterpret_cast<ps::BatchCtl*>(head->ws + head->off_batch + L.ctl);
-    a.sol = reinterpret_cast<const ps::BatchSolve*>(head->ws + head->off_batch + L.sol);
-    a.prefix = reinterpret_cast<const int*>(head->ws + head->off_batch + L.prefix);
-    a.done = reinterpret_cast<unsigned*>(head->ws + head->off_batch + L.done);
-    a.nsolves = count;
-    a.total = ctl->total;
-    a.stab = reinterpret_cast<const unsigned short*>(head->ws + head->off_tab + head->split_tab);
-    a.spin_limit = 1u << 20;
-    a.stream = st;
-    hipError_t e = a.kind == 2 ? ps::batched_run_f64(a) : (a.kind == 1 ? ps::batched_run_split(a) : ps::batched_run_f32(a));
-    if (e != hipSuccess) return device_fail(e, "batched launch");
-    return PS_OK;
-}
-
-ps_status ps_batch_check(ps_plan first, void* stream, int* error)
-{
-    if (ps_status s = check_plan(first)) return s;
-    if (!error) return fail(PS_ERR_INVALID, "error is NULL");
-    if (first->batch_sig.empty()) return fail(PS_ERR_NOT_READY, "this plan has not led a batch");
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return device_fail(e, "batch synchronise");
-    unsigned flag = 0;
-    e = hipMemcpy(&flag, first->ws + first->off_batch + offsetof(ps::BatchCtl, error), sizeof(flag),
-                  hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return device_fail(e, "batch status read");
-    *error = flag ? 1 : 0;
+    for (int pass = 0; pass < 5; ++pass) {
+        for (int k0 = 0; k0 < count;) {
+            const ps_plan p0 = plans[order[k0]];
+            ps::PrunedVariant v0 = p0->var;
+            int k1 = k0 + 1;
+            while (k1 < count) {
+                ps::PrunedVariant v1 = plans[order[k1]]->var;
+                if (plans[order[k1]]->P != p0->P || *variant_slot(v1, pass) != *variant_slot(v0, pass) ||
+                    v1.mterms != v0.mterms)
+                    break;
+                ++k1;
+            }
+            ps::PrunedBufs b = pruned_bufs(p0, nullptr, nullptr, st);
+            b.list = dlist + k0;
+            b.count = k1 - k0;
+            const hipError_t e = run_pruned(prec, p0->P, pass, pass + 1, b);
+            if (e != hipSuccess) return device_fail(e, "batched launch");
+            k0 = k1;
+        }
+    }
     return PS_OK;
 }
 

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/ps.h"
+#include "solve_rec.hpp"
 
 namespace ps {
 
@@ -21,22 +22,19 @@ struct PrunedVariant {
 };
 constexpr int NUM_ZMODES = 3;
 
-// Device buffers of one solve of the pruned pipeline.  Complex arrays are
-// interleaved (re, im) of the plan's real type.
+// Launch arguments of the pruned pipeline: `count` equal-length solves whose
+// records are the device array `list` (grid z indexes it).  in[k] / out[k],
+// when not NULL, replace pass k's input / output array of the record (a
+// single solve's rho and phi, or the arrays of a debug pass).  Complex arrays
+// are interleaved (re, im) of the plan's real type.
 struct PrunedBufs {
-    const void* rho;   // N^3 real
-    void* phi;         // N^3 real
-    void* t1;          // T1 [H][N][N] complex; later T4 [N][N][HP]
-    void* t2;          // T2 [H][P][N] complex
-    void* t3;          // T3 [H][N][P] complex
-    const void* ghat;  // [H][H][H] real octant, scaled
-    const void* twf;   // forward-plan twiddles, family 0
-    const void* twi;   // inverse-plan twiddles, family 0
-    const void* twf1;  // forward-plan twiddles, family 1
-    const void* twi1;  // inverse-plan twiddles, family 1
-    const unsigned short* stab;  // split-bf16 DFT-16 matrix pieces (mterms > 0)
+    const SolveRec* list = nullptr;
+    int count = 1;
+    const void* in[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    void* out[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const unsigned short* stab = nullptr;  // split-bf16 DFT-16 matrix pieces (mterms > 0)
     PrunedVariant var;
-    hipStream_t stream;
+    hipStream_t stream = nullptr;
 };
 
 // Runs passes [lo, hi) of the pruned pipeline (0 x_r2c, 1 y_fwd, 2 z_conv,
@@ -71,25 +69,6 @@ struct PlainBufs {
 };
 hipError_t plain_run_f32(int P, const PlainBufs& b);
 hipError_t plain_run_f64(int P, const PlainBufs& b);
-
-// One persistent batched launch (plus the reset of its counters).
-struct BatchCtl;
-struct BatchSolve;
-struct BatchArgs {
-    int kind;  // 0 float, 1 float + split-bf16 DFT-16 (6 terms), 2 double
-    int pmax;  // largest padded length in the batch
-    BatchCtl* ctl;
-    const BatchSolve* sol;
-    const int* prefix;
-    unsigned* done;
-    int nsolves, total;
-    const unsigned short* stab;
-    unsigned spin_limit;
-    hipStream_t stream;
-};
-hipError_t batched_run_f32(const BatchArgs& a);
-hipError_t batched_run_split(const BatchArgs& a);
-hipError_t batched_run_f64(const BatchArgs& a);
 
 // Radix plans (forward; the inverse is the reverse) for a supported P and
 // plan family; family 1 falls back to family 0 where it does not exist.

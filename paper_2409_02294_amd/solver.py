@@ -39,7 +39,7 @@ SUPPORTED_N = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 EXPORTS = ("ps_plan_create", "ps_plan_workspace_bytes", "ps_plan_query", "ps_green_build", "ps_solve",
            "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass",
-           "ps_plan_set_variant", "ps_autotune", "ps_batch_check")
+           "ps_plan_set_variant", "ps_autotune")
 
 
 class PSError(RuntimeError):
@@ -86,7 +86,6 @@ def load() -> ctypes.CDLL:
         "ps_debug_pass": ([vp, i, vp, vp, vp], i),
         "ps_plan_set_variant": ([vp, i, i], i),
         "ps_autotune": ([vp, vp, ctypes.c_char_p], i),
-        "ps_batch_check": ([vp, vp, ctypes.POINTER(i)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -146,12 +145,6 @@ def ps_solve_batched(plans: Sequence[int], rho: Sequence[int], phi: Sequence[int
         raise ValueError("plans, rho and phi must have equal length")
     arr = ctypes.c_void_p * max(n, 1)
     _check(load().ps_solve_batched(arr(*plans), n, arr(*rho), arr(*phi), stream), "ps_solve_batched")
-
-
-def ps_batch_check(plan: int, stream: int) -> int:
-    err = ctypes.c_int()
-    _check(load().ps_batch_check(plan, stream, ctypes.byref(err)), "ps_batch_check")
-    return err.value
 
 
 def ps_plan_destroy(plan: int) -> None:
@@ -232,7 +225,7 @@ class Solver:
 
 
 def solve_batched(solvers: List[Solver], rhos, outs=None):
-    """One persistent launch over several solvers' densities."""
+    """One batched solve (five grouped launches) over several solvers' densities."""
     import torch
     if outs is None:
         outs = [torch.empty_like(r) for r in rhos]
