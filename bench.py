@@ -62,9 +62,9 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n: int, prec: str):
+def measured_traffic(kernel: str, n: int, prec: str, variant: int):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources with the same kernel variant; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -72,7 +72,7 @@ def measured_traffic(kernel: str, n: int, prec: str):
         with open(path) as fh:
             d = json.load(fh)
         rec = d["kernels"][f"{kernel}/n{n}/{prec}"]
-        if rec.get("source_hash") != source_hash():
+        if rec.get("source_hash") != source_hash() or rec.get("variant") != variant:
             return None
         return float(rec["bytes_per_launch"])
     except Exception:
@@ -344,6 +344,13 @@ def ingest_counters(args) -> int:
     fac = {w: copy_kib / avg[w]["copy"] for w in ("fetch", "write")}
     rb = 8 if args.precision.startswith("f64") else 4
     pb = pass_bytes(args.n, rb)
+    if args.variants:
+        variants = [int(x) for x in args.variants.split(",")]
+    else:  # the library defaults (plan creation makes no HIP call)
+        from paper_2409_02294_amd import solver as S
+        plan = S.ps_plan_create(args.n, 1.0 / args.n, S.PRECISIONS[args.precision], None)
+        variants = S.ps_plan_query(plan)["variant"]
+        S.ps_plan_destroy(plan)
     out_path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.json")
     doc = {"about": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each "
                     "scaled by the factor that makes a 1 GiB elementwise copy read and write 1 GiB",
@@ -360,7 +367,7 @@ def ingest_counters(args) -> int:
             "fetch_KiB_raw": avg["fetch"][k], "write_KiB_raw": avg["write"][k],
             "bytes_per_launch": (f + w) * 1024.0, "read_bytes": f * 1024.0, "write_bytes": w * 1024.0,
             "algorithmic_bytes": pb[k], "ratio_to_algorithmic": (f + w) * 1024.0 / pb[k],
-            "source_hash": source_hash(),
+            "variant": variants[PASS_NAMES.index(k)], "source_hash": source_hash(),
         }
     with open(out_path, "w") as fh:
         json.dump(doc, fh, indent=1)
@@ -378,7 +385,9 @@ def main() -> int:
     ap.add_argument("--compare", default="f32_split,f64,f64_plain", help="other precisions timed beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel variants")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune each pass's kernel variant live instead of the library defaults "
+                         "(measured fastest on MI355X)")
     ap.add_argument("--pass-loop", type=int, default=0, metavar="K",
                     help="instead of the benchmark: run each pass of one solve K times, then a 1 GiB "
                          "elementwise copy K times (the target of the HBM counter runs)")
@@ -430,7 +439,7 @@ def main() -> int:
         dt = torch.float64 if prec.startswith("f64") else torch.float32
         rho = torch.from_numpy(rho_np).to("cuda", dt)
         phi = torch.empty_like(rho)
-        if not prec.endswith("plain") and not args.no_tune:
+        if not prec.endswith("plain") and args.retune:
             # the autotuner picks each pass's fastest kernel variant (outside the timed region)
             S.ps_autotune(s.plan, torch.cuda.current_stream().cuda_stream, None)
         steps = args.steps if prec == head else max(3, args.steps // 4)
@@ -495,7 +504,7 @@ def main() -> int:
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBS,
-            "traffic": measured_traffic(kname, n, head),
+            "traffic": measured_traffic(kname, n, head, hr["variants"][dom]),
             "algorithmic_bytes_per_launch": pb[kname],
             "avg_launch_ms": pass_ms[dom],
         }

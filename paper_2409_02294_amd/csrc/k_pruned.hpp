@@ -40,6 +40,26 @@ __host__ __device__ constexpr int t4_pitch(int H) { return (H + 15) / 16 * 16; }
 // coordinates, using a caller-provided LDS buffer of at least LDS elements),
 // wrapped below as a one-tile-per-workgroup kernel.
 
+// Element-wise copy of COUNT items src(e) -> dst(e, v) by the NT threads of a
+// workgroup, each thread issuing all its loads before its stores, so a tile
+// waits one memory latency rather than one per element it stages.
+template <typename V, int NT, int COUNT, class SRC, class DST>
+__device__ __forceinline__ void block_copy(SRC&& src, DST&& dst)
+{
+    constexpr int K = (COUNT + NT - 1) / NT;
+    V tmp[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
+        if (COUNT % NT == 0 || e < COUNT) tmp[i] = src(e);
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
+        if (COUNT % NT == 0 || e < COUNT) dst(e, tmp[i]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // x_r2c: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
 // ---------------------------------------------------------------------------
@@ -64,21 +84,21 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXR
         E::template run<-1, MAP_EF, MAP_MID, MAP_EF, N, P, true>(lds, tw, ld, st, sa);
         __syncthreads();
         V* t1z = t1 + (size_t)z * N;
-        for (int e = threadIdx.x; e < 16 * H; e += NT) {
+        // separate the two half spectra of each packed pair: element e is
+        // (row e % 16, k = e / 16), written to T1[k][z][y0 + row]
+        auto sep = [&](int e) -> V {
             const int row = e & 15, k = e >> 4;
-            const int y = y0 + row;
-            if (y >= N) continue;
             const int p = row >> 1;
             const V z1 = lds[E::lidx(p, k)];
             const V z2 = lds[E::lidx(p, k == 0 ? 0 : P - k)];
-            V x;
-            if (row & 1) {
-                x = V{T(0.5) * (z1.y + z2.y), T(-0.5) * (z1.x - z2.x)};
-            } else {
-                x = V{T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
-            }
-            t1z[(unsigned)(k * N * N + y)] = x;
-        }
+            if (row & 1) return V{T(0.5) * (z1.y + z2.y), T(-0.5) * (z1.x - z2.x)};
+            return V{T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
+        };
+        auto put = [&](int e, V x) {
+            const int row = e & 15, k = e >> 4;
+            if (y0 + row < N) t1z[(unsigned)(k * N * N + y0 + row)] = x;
+        };
+        block_copy<V, NT, 16 * H>(sep, put);
     }
 };
 
@@ -187,10 +207,15 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXC
         const int y0 = bx * 16;
         const int z = by;
         const V* rows = t4 + ((size_t)z * N + y0) * HP;  // 16 consecutive rows of H (pitch HP)
-        for (int e = threadIdx.x; e < 16 * H; e += NT) {
-            const int row = e / H, k = e - row * H;
-            lds[row * XP + k] = y0 + row < N ? rows[(unsigned)(row * HP + k)] : V{T(0), T(0)};
-        }
+        block_copy<V, NT, 16 * H>(
+            [&](int e) -> V {
+                const int row = e / H, k = e - row * H;
+                return y0 + row < N ? rows[(unsigned)(row * HP + k)] : V{T(0), T(0)};
+            },
+            [&](int e, V v) {
+                const int row = e / H, k = e - row * H;
+                lds[row * XP + k] = v;
+            });
         __syncthreads();
         auto ld = [&](int p, int idx) -> V {
             const V* xa = lds + (2 * p) * XP;
@@ -269,6 +294,23 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* in, cx<T>* out, const
             sa);
 }
 
+// z-pass tile order.  Pencils ky and P - ky multiply by the same Ghat rows,
+// so tile t of a kx (NTILE tiles of B pencils) shares all but one of its
+// rows with tile NTILE - 1 - t.  Workgroups go to the XCDs round-robin by
+// linear index (here blockIdx.x mod 8, NTILE being a multiple of 8), so in
+// launch order a tile and its mirror land on different XCDs and fetch the
+// rows into two L2s.  Remapped, linear indices 16 g + x and 16 g + 8 + x
+// (the same XCD, consecutive there) hold pair q = 8 g + x and its mirror.
+template <int NTILE> __device__ __forceinline__ int z_tile(int l)
+{
+    if constexpr (NTILE % 16 != 0) {
+        return l;
+    } else {
+        const int q = (l & 7) + 8 * (l >> 4);
+        return (l & 8) ? NTILE - 1 - q : q;
+    }
+}
+
 template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT>
 __global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
                                                const unsigned short* __restrict__ stab)
@@ -279,8 +321,8 @@ __global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, cons
     typename TL::EF::SA sa;
     sa.load(stab);
     const SolveRec& s = list[blockIdx.z];
-    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t2), out ? out : gp<V>(s.t3), gp<const T>(s.ghat),
-            tw_fwd<V, FAM>(s), tw_inv<V, FAM>(s), lds, sa);
+    TL::run(z_tile<P / B>(blockIdx.x), blockIdx.y, in ? in : gp<const V>(s.t2), out ? out : gp<V>(s.t3),
+            gp<const T>(s.ghat), tw_fwd<V, FAM>(s), tw_inv<V, FAM>(s), lds, sa);
 }
 
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>

@@ -393,14 +393,18 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
         p->tables.resize(p->split_tab + st.size() * sizeof(unsigned short), 0);
         std::memcpy(p->tables.data() + p->split_tab, st.data(), st.size() * sizeof(unsigned short));
     }
-    // default variants: wave-owned z pass; family 1 where it exists (not for
-    // split plans, whose matrix-core stages are the radix-16 ones)
+    // Default variants, as measured fastest per pass on MI355X: wave-owned
+    // z pass; where the radix-32-based family exists (P = 512, 1024) it wins
+    // for the forward y pass and, in FP32, the z pass, while the x passes and
+    // the inverse y pass keep the radix-16-based family.  Split plans keep
+    // the radix-16 stages (their matrix-core DFT-16); at P = 1024 their
+    // workgroup-synchronised z pass is faster.
     if (prec == PS_F32_SPLIT) {
-        p->var.zmode = 1;
+        p->var.zmode = p->P >= 1024 ? 0 : 1;
         p->var.mterms = 6;
     } else if (ps::has_family1(p->P)) {
-        p->var.x_fam = p->var.y_fam = p->var.yi_fam = p->var.xc_fam = 1;
-        p->var.zmode = 2;
+        p->var.y_fam = 1;
+        p->var.zmode = (prec == PS_F64 && p->P >= 1024) ? 1 : 2;
     } else {
         p->var.zmode = 1;
     }

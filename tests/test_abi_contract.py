@@ -168,12 +168,20 @@ def test_tuning_cache_is_read(tmp_path):
         assert S.ps_plan_query(p)["variant"] == [0, 1, 1, 0, 1]
     finally:
         S.ps_plan_destroy(p)
-    # a missing file keeps the defaults
+    # a missing file keeps the defaults (radix-32 family for the forward y pass
+    # and the FP32 z pass at P = 512, radix-16 family elsewhere)
     p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32, str(tmp_path / "absent.txt"))
     try:
-        assert S.ps_plan_query(p)["variant"] == [1, 1, 2, 1, 1]
+        assert S.ps_plan_query(p)["variant"] == [0, 1, 2, 0, 0]
     finally:
         S.ps_plan_destroy(p)
+    for n, prec, want in [(512, S.PS_F32, [0, 1, 2, 0, 0]), (512, S.PS_F64, [0, 1, 1, 0, 0]),
+                          (128, S.PS_F32, [0, 0, 1, 0, 0]), (512, S.PS_F32_SPLIT, [0, 0, 0, 0, 0])]:
+        p = S.ps_plan_create(n, 1.0 / n, prec, None)
+        try:
+            assert S.ps_plan_query(p)["variant"] == want, (n, prec)
+        finally:
+            S.ps_plan_destroy(p)
 
 
 def test_split_plan_contract():
