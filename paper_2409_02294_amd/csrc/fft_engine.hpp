@@ -31,9 +31,14 @@
 // exchanges synchronise the wavefront only, not the workgroup.
 //
 // Twiddles come from a per-plan table computed in double precision on the
-// host and rounded once to T: for stage s >= 1 a row of R entries per
-// residue m = j mod NS, entry r = exp(-2 pi i r m / (NS R)); the inverse
-// direction uses the conjugate.
+// host and rounded once to T: for stage s >= 1 and residue m = j mod NS,
+// entry r is exp(-2 pi i r m / (NS R)) (the inverse direction uses the
+// conjugate).  The table holds every stage twice: by rows (m major, R
+// entries per residue) and by columns (r major, NS entries per r).  A stage
+// whose lanes run over consecutive butterflies (MAP_EF, MAP_WV) reads
+// columns, one contiguous span per wavefront load; a stage whose lanes run
+// over pencils first (MAP_PF, where groups of B lanes share a residue) reads
+// rows, a few wide loads per lane.
 #pragma once
 #include <type_traits>
 
@@ -53,7 +58,8 @@ template <int... Rs> struct Radices {
         for (int i = 0; i < s; ++i) v *= r[i];
         return v;
     }
-    // offset (complex entries) of stage s's twiddle rows
+    // offset (complex entries) of stage s's twiddle rows; its columns follow
+    // all the rows, at tw_size() + tw_off(s)
     static constexpr int tw_off(int s)
     {
         int o = 0;
@@ -265,10 +271,17 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
                 int p, j;
                 pj<s, MAP>(b, p, j);
                 if (valid<s, MAP>(b)) {
-                    const V* row = tw + RP::tw_off(s) + (j % NSs) * Rs + ro;
+                    if constexpr (MAP == MAP_PF) {
+                        const V* row = tw + RP::tw_off(s) + (j % NSs) * Rs + ro;
 #pragma unroll
-                    for (int q = 0; q < RS<s>; ++q)
-                        if (MF<s> || q > 0) g.v[i][q] = ctw<DIR>(g.v[i][q], row[q]);
+                        for (int q = 0; q < RS<s>; ++q)
+                            if (MF<s> || q > 0) g.v[i][q] = ctw<DIR>(g.v[i][q], row[q]);
+                    } else {
+                        const V* col = tw + RP::tw_size() + RP::tw_off(s) + ro * NSs + (j % NSs);
+#pragma unroll
+                        for (int q = 0; q < RS<s>; ++q)
+                            if (MF<s> || q > 0) g.v[i][q] = ctw<DIR>(g.v[i][q], col[q * NSs]);
+                    }
                 }
             }
             if constexpr (MF<s>) dft16_split<MT, DIR>(g.v[i], sa);

@@ -74,23 +74,29 @@ void unit_root(long a, long L, double& c, double& s)
     }
 }
 
-// Twiddle rows of a radix plan (stages >= 1): per residue m < NS a row of R
-// entries exp(-2 pi i r m / (NS R)).
+// Twiddle tables of a radix plan (stages >= 1), entry (q, m) =
+// exp(-2 pi i q m / (NS R)) for q < R and residue m < NS: first every stage
+// by rows (m major), then every stage by columns (q major), matching
+// Radices::tw_off and tw_size on the device.
 std::vector<std::complex<double>> plan_table(const std::vector<int>& rad)
 {
-    std::vector<std::complex<double>> t;
+    std::vector<std::complex<double>> rows, cols;
     long ns = rad.empty() ? 1 : rad[0];
     for (size_t s = 1; s < rad.size(); ++s) {
         const long r = rad[s];
+        auto w = [&](long q, long m) {
+            double c, sn;
+            unit_root(q * m, ns * r, c, sn);
+            return std::complex<double>(c, -sn);
+        };
         for (long m = 0; m < ns; ++m)
-            for (long q = 0; q < r; ++q) {
-                double c, sn;
-                unit_root(q * m, ns * r, c, sn);
-                t.emplace_back(c, -sn);
-            }
+            for (long q = 0; q < r; ++q) rows.push_back(w(q, m));
+        for (long q = 0; q < r; ++q)
+            for (long m = 0; m < ns; ++m) cols.push_back(w(q, m));
         ns *= r;
     }
-    return t;
+    rows.insert(rows.end(), cols.begin(), cols.end());
+    return rows;
 }
 
 // Round a double to the nearest bf16 value (8 significant bits, ties to even).
