@@ -202,6 +202,16 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
     static constexpr int LP = P + P / 16 + 1;
     static constexpr int LDS_ELEMS = B * LP;
 
+    // Twiddle source: the row and column layouts of the plan's table.  A
+    // plain table pointer holds both (columns after all the rows); a kernel
+    // may instead point the columns at a copy in LDS.
+    struct TW {
+        const V* rows;
+        const V* cols;
+        __device__ __forceinline__ TW(const V* t) : rows(t), cols(t + RP::tw_size()) {}
+        __device__ __forceinline__ TW(const V* r, const V* c) : rows(r), cols(c) {}
+    };
+
     template <int s> static constexpr int R = RP::r[s];
     template <int s> static constexpr int Q = P / RP::r[s];
     template <int s> static constexpr int BF = B * (P / RP::r[s]);
@@ -259,7 +269,7 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
 
     // Stage-s twiddles and DFT on every slot this thread owns.
     template <int s, int DIR, int MAP>
-    __device__ __forceinline__ static void compute(Regs<s>& g, const V* __restrict__ tw, const SA& sa)
+    __device__ __forceinline__ static void compute(Regs<s>& g, const TW& tw, const SA& sa)
     {
         constexpr int Rs = R<s>;
         constexpr int NSs = RP::ns(s);
@@ -272,12 +282,12 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
                 pj<s, MAP>(b, p, j);
                 if (valid<s, MAP>(b)) {
                     if constexpr (MAP == MAP_PF) {
-                        const V* row = tw + RP::tw_off(s) + (j % NSs) * Rs + ro;
+                        const V* row = tw.rows + RP::tw_off(s) + (j % NSs) * Rs + ro;
 #pragma unroll
                         for (int q = 0; q < RS<s>; ++q)
                             if (MF<s> || q > 0) g.v[i][q] = ctw<DIR>(g.v[i][q], row[q]);
                     } else {
-                        const V* col = tw + RP::tw_size() + RP::tw_off(s) + ro * NSs + (j % NSs);
+                        const V* col = tw.cols + RP::tw_off(s) + ro * NSs + (j % NSs);
 #pragma unroll
                         for (int q = 0; q < RS<s>; ++q)
                             if (MF<s> || q > 0) g.v[i][q] = ctw<DIR>(g.v[i][q], col[q * NSs]);
@@ -424,10 +434,35 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
         }
     }
 
+    // out[i][q] = f(p, idx) for every element held after stage s, in the
+    // layout of Regs<s> (slots this thread does not own are zero).
+    template <int s, int MAP, class F>
+    __device__ __forceinline__ static void gather(T (&out)[NB<s>][RS<s>], F& f)
+    {
+        const int vt = vthread<s>(), ro = roff<s>();
+#pragma unroll
+        for (int i = 0; i < NB<s>; ++i) {
+            const int b = vt + i * NTV<s>;
+            const bool ok = valid<s, MAP>(b);
+            int p, j;
+            pj<s, MAP>(b, p, j);
+#pragma unroll
+            for (int q = 0; q < RS<s>; ++q) out[i][q] = ok ? f(p, j + (ro + q) * Q<s>) : T(0);
+        }
+    }
+    // g *= w element by element (w real, laid out like Regs<s>).
+    template <int s> __device__ __forceinline__ static void scale(Regs<s>& g, const T (&w)[NB<s>][RS<s>])
+    {
+#pragma unroll
+        for (int i = 0; i < NB<s>; ++i)
+#pragma unroll
+            for (int q = 0; q < RS<s>; ++q) g.v[i][q] = V{g.v[i][q].x * w[i][q], g.v[i][q].y * w[i][q]};
+    }
+
     // Middle stages [S0, S1) through LDS with mapping MAP; MPREV is the
     // mapping of the stage that wrote the LDS before stage S0.
     template <int s, int S1, int DIR, int MAP, int MPREV>
-    __device__ __forceinline__ static void middle(V* lds, const V* tw, const SA& sa)
+    __device__ __forceinline__ static void middle(V* lds, const TW& tw, const SA& sa)
     {
         if constexpr (s < S1) {
             Regs<s> g;
@@ -446,7 +481,7 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
     // into the same LDS buffer, so a barrier separates the last reads from
     // those writes.
     template <int DIR, int MAP_IN, int MAP_MID, int MAP_OUT, int LIN, int LOUT, bool DST_LDS = false, class LD, class ST>
-    __device__ __forceinline__ static void run(V* lds, const V* __restrict__ tw, LD& ld, ST& st, const SA& sa = SA{})
+    __device__ __forceinline__ static void run(V* lds, const TW& tw, LD& ld, ST& st, const SA& sa = SA{})
     {
         if constexpr (S == 1) {
             Regs<0> g;
@@ -497,7 +532,7 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
     // Forward stages ending in registers: the last stage's outputs for each
     // owned butterfly (p, j) sit in g.v[i][r] at natural index j + r P/R.
     template <int DIR, int MAP_IN, int MAP_MID, int MAP_OUT, int LIN, class LD>
-    __device__ __forceinline__ static void run_to_regs(V* lds, const V* __restrict__ tw, LD& ld, Regs<S - 1>& out,
+    __device__ __forceinline__ static void run_to_regs(V* lds, const TW& tw, LD& ld, Regs<S - 1>& out,
                                                        const SA& sa = SA{})
     {
         if constexpr (S == 1) {
@@ -519,10 +554,28 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
         }
     }
 
+    // As run_to_regs, with the stage-0 inputs already in registers (loaded
+    // by load_first earlier, e.g. one tile ahead).  The first LDS exchange
+    // synchronises only as MAP_IN requires: a caller reusing the LDS across
+    // tiles separates the tiles with a workgroup barrier.
+    template <int DIR, int MAP_IN, int MAP_MID, int MAP_OUT>
+    __device__ __forceinline__ static void run_to_regs_loaded(V* lds, const TW& tw, Regs<0>& g, Regs<S - 1>& out,
+                                                              const SA& sa = SA{})
+    {
+        static_assert(S > 1, "single-stage plans load and compute in one step");
+        compute<0, DIR, MAP_IN>(g, tw, sa);
+        sync2<MAP_IN, MAP_IN>();
+        store_lds<0, MAP_IN>(g, lds);
+        middle<1, S - 1, DIR, MAP_MID, MAP_IN>(lds, tw, sa);
+        sync2<map_before_last<MAP_IN, MAP_MID>, MAP_OUT>();
+        load_lds<S - 1, MAP_OUT>(out, lds);
+        compute<S - 1, DIR, MAP_OUT>(out, tw, sa);
+    }
+
     // Stages starting from registers that already hold the stage-0 inputs
     // (index j + r P/R for each owned butterfly (p, j) under MAP_IN).
     template <int DIR, int MAP_IN, int MAP_MID, int MAP_OUT, int LOUT, class ST>
-    __device__ __forceinline__ static void run_from_regs(V* lds, const V* __restrict__ tw, Regs<0>& g, ST& st,
+    __device__ __forceinline__ static void run_from_regs(V* lds, const TW& tw, Regs<0>& g, ST& st,
                                                          const SA& sa = SA{})
     {
         if constexpr (S == 1) {

@@ -27,6 +27,8 @@
 // kz' = min(kz, P-kz)) of the transformed kernel, already scaled by
 // G dx^3 / P^3, so the pipeline itself applies no normalisation.
 #pragma once
+#include <type_traits>
+
 #include "plans.hpp"
 #include "solve_rec.hpp"
 
@@ -323,6 +325,88 @@ __global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, cons
     const SolveRec& s = list[blockIdx.z];
     TL::run(z_tile<P / B>(blockIdx.x), blockIdx.y, in ? in : gp<const V>(s.t2), out ? out : gp<V>(s.t3),
             gp<const T>(s.ghat), tw_fwd<V, FAM>(s), tw_inv<V, FAM>(s), lds, sa);
+}
+
+// z_conv, persistent, with a one-tile prefetch (wave-owned pencils).  Each
+// workgroup walks tiles blockIdx.x, + gridDim.x, ... of all `count` solves
+// (the grid is a multiple of 8, so the XCD pairing of z_tile holds).  Per
+// tile it first issues the loads of the tile's kernel values, then those of
+// the next tile's pencils, and only then transforms the current pencils, so
+// memory latency overlaps arithmetic instead of stalling each tile's start.
+// Vector loads complete in issue order, so a global twiddle load inside the
+// transforms would also wait for the prefetch: the column twiddles (every
+// stage but the last inverse one) are copied to LDS once per workgroup; the
+// last inverse stage reads its row twiddles from global memory after the
+// tile's arithmetic.
+template <typename T, int P, int FAM, int B, int NT, int MT>
+__global__ __launch_bounds__(NT) void k_z_conv_pf(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                                  const unsigned short* __restrict__ stab, int count)
+{
+    using TL = TileZConv<T, P, FAM, B, NT, true, MT>;
+    using EF = typename TL::EF;
+    using EI = typename TL::EI;
+    using V = cx<T>;
+    using RF = typename PlanFor<P, FAM>::Fwd;
+    using RI = typename PlanFor<P, FAM>::Inv;
+    constexpr int N = P / 2, H = N + 1, NTILE = P / B, SL = EF::S - 1;
+    constexpr bool SAME = std::is_same<RF, RI>::value;  // palindromic plan: one table serves both directions
+    constexpr int CF = RF::tw_size(), CI = SAME ? 0 : RI::tw_size();
+    __shared__ V lds[TL::LDS];
+    __shared__ V lcol[CF + CI];
+    typename EF::SA sa;
+    sa.load(stab);
+    const int total = NTILE * H * count;
+    int t = blockIdx.x;
+    if (t >= total) return;
+    {
+        // columns follow the rows in each table; one plan serves every record of a launch
+        const V* cf = tw_fwd<V, FAM>(list[0]) + CF;
+        for (int e = threadIdx.x; e < CF; e += NT) lcol[e] = cf[e];
+        if constexpr (!SAME) {
+            const V* ci = tw_inv<V, FAM>(list[0]) + RI::tw_size();
+            for (int e = threadIdx.x; e < CI; e += NT) lcol[CF + e] = ci[e];
+        }
+        __syncthreads();
+    }
+    auto tile = [&](int u, int& zs, int& kx, int& ky0) {
+        zs = u / (NTILE * H);
+        const int r = u - zs * (NTILE * H);
+        kx = r / NTILE;
+        ky0 = z_tile<NTILE>(r - kx * NTILE) * B;
+    };
+    auto load = [&](int u, typename EF::template Regs<0>& g) {
+        int zs, kx, ky0;
+        tile(u, zs, kx, ky0);
+        const V* pin = (in ? in : gp<const V>(list[zs].t2)) + ((size_t)kx * P + ky0) * N;
+        auto ld = [&](int p, int idx) -> V { return pin[(unsigned)(p * N + idx)]; };
+        EF::template load_first<MAP_WV, N>(g, ld);
+    };
+    typename EF::template Regs<0> cur;
+    load(t, cur);
+    for (; t < total; t += gridDim.x) {
+        int zs, kx, ky0;
+        tile(t, zs, kx, ky0);
+        const SolveRec& s = list[zs];
+        const T* grow = gp<const T>(s.ghat) + (size_t)kx * H * H;
+        auto gk = [&](int p, int kz) -> T {
+            const int ky = ky0 + p;
+            return grow[(unsigned)((ky <= N ? ky : P - ky) * H + (kz <= N ? kz : P - kz))];
+        };
+        T gv[EF::template NB<SL>][EF::template RS<SL>];
+        EF::template gather<SL, MAP_WV>(gv, gk);
+        typename EF::template Regs<0> nxt;
+        if (t + (int)gridDim.x < total) load(t + gridDim.x, nxt);
+        typename EF::template Regs<SL> g;
+        EF::template run_to_regs_loaded<-1, MAP_WV, MAP_WV, MAP_WV>(
+            lds, typename EF::TW(tw_fwd<V, FAM>(s), lcol), cur, g, sa);
+        EF::template scale<SL>(g, gv);
+        V* pout = (out ? out : gp<V>(s.t3)) + (size_t)kx * N * P + ky0;
+        auto st = [&](int p, int idx, V v) { pout[(unsigned)(idx * P + p)] = v; };
+        EI::template run_from_regs<+1, MAP_WV, MAP_WV, MAP_PF, N>(
+            lds, typename EI::TW(tw_inv<V, FAM>(s), SAME ? lcol : lcol + CF), g, st, sa);
+        __syncthreads();  // the last stage read every pencil's rows; the next tile rewrites them
+        cur = nxt;
+    }
 }
 
 template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>

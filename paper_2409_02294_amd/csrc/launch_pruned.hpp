@@ -44,6 +44,28 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
         hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H, b.count), dim3(NTZ), 0, b.stream,
                            static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab);
     }
+    // Persistent z pass: as many workgroups as fit on the device at once (a
+    // multiple of 8, so tile pairs stay on one XCD), each walking the tiles.
+    static void z_conv_pf(const PrunedBufs& b)
+    {
+        constexpr int NTZ = wave_threads(ZB, P, E);
+        static int resident = 0;
+        if (resident == 0) {
+            int dev = 0, cus = 0, per_cu = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>, NTZ, 0) ==
+                    hipSuccess &&
+                per_cu * cus >= 8)
+                resident = per_cu * cus / 8 * 8;
+            else
+                resident = 1024;
+        }
+        const int total = (P / ZB) * H * b.count;
+        const int grid = total < resident ? total : resident;
+        hipLaunchKernelGGL((k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>), dim3(grid), dim3(NTZ), 0, b.stream,
+                           static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab, b.count);
+    }
     static void y_inv(const PrunedBufs& b)
     {
         hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((H + ZT - 1) / ZT, N, b.count), dim3(NTY),
@@ -74,7 +96,13 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else L0::y_fwd(b);
             break;
         case 2:
-            if (v.zmode == 2 && F1) L1::template z_conv<true>(b);
+            if constexpr (F1) {
+                if (v.zmode == 3) {
+                    L1::z_conv_pf(b);
+                    break;
+                }
+            }
+            if (v.zmode >= 2 && F1) L1::template z_conv<true>(b);
             else if (v.zmode >= 1) L0::template z_conv<true>(b);
             else L0::template z_conv<false>(b);
             break;

@@ -401,16 +401,17 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     }
     // Default variants, as measured fastest per pass on MI355X: wave-owned
     // z pass; where the radix-32-based family exists (P = 512, 1024) it wins
-    // for the forward y pass and, in FP32, the z pass, while the x passes and
-    // the inverse y pass keep the radix-16-based family.  Split plans keep
-    // the radix-16 stages (their matrix-core DFT-16); at P = 1024 their
-    // workgroup-synchronised z pass is faster.
+    // for the forward y pass and, in FP32, the z pass (its persistent,
+    // prefetching form), while the x passes and the inverse y pass keep the
+    // radix-16-based family.  Split plans keep the radix-16 stages (their
+    // matrix-core DFT-16); at P = 1024 their workgroup-synchronised z pass is
+    // faster.
     if (prec == PS_F32_SPLIT) {
         p->var.zmode = p->P >= 1024 ? 0 : 1;
         p->var.mterms = 6;
     } else if (ps::has_family1(p->P)) {
         p->var.y_fam = 1;
-        p->var.zmode = (prec == PS_F64 && p->P >= 1024) ? 1 : 2;
+        p->var.zmode = prec == PS_F64 ? (p->P >= 1024 ? 1 : 2) : 3;
     } else {
         p->var.zmode = 1;
     }

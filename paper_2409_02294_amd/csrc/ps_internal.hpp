@@ -15,12 +15,13 @@ namespace ps {
 // Kernel variants of the pruned pipeline (chosen per plan, e.g. by the
 // autotuner).  fam: radix-plan family (0: radix-16 based, 1: radix-32 based
 // where P allows it, else 0).  zmode: 0 workgroup-synchronised z pass,
-// 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1).
+// 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1),
+// 3 persistent wave-owned pencils with a one-tile prefetch (family 1).
 struct PrunedVariant {
     int x_fam = 0, y_fam = 0, zmode = 0, yi_fam = 0, xc_fam = 0;
     int mterms = 0;  // 0: vector-ALU DFTs; 3 or 6: split-bf16 matrix-core radix-16 DFTs (float only)
 };
-constexpr int NUM_ZMODES = 3;
+constexpr int NUM_ZMODES = 4;
 
 // Launch arguments of the pruned pipeline: `count` equal-length solves whose
 // records are the device array `list` (grid z indexes it).  in[k] / out[k],

@@ -144,7 +144,7 @@ def test_variant_selection_contract():
         lib = S.load()
         assert lib.ps_plan_set_variant(p, 6, 0) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 5, 6) == S.PS_ERR_UNSUPPORTED  # product terms: split plans only
-        assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 2, 4) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED  # no radix-32 family at P = 64
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
@@ -172,10 +172,11 @@ def test_tuning_cache_is_read(tmp_path):
     # and the FP32 z pass at P = 512, radix-16 family elsewhere)
     p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32, str(tmp_path / "absent.txt"))
     try:
-        assert S.ps_plan_query(p)["variant"] == [0, 1, 2, 0, 0]
+        assert S.ps_plan_query(p)["variant"] == [0, 1, 3, 0, 0]
     finally:
         S.ps_plan_destroy(p)
-    for n, prec, want in [(512, S.PS_F32, [0, 1, 2, 0, 0]), (512, S.PS_F64, [0, 1, 1, 0, 0]),
+    for n, prec, want in [(512, S.PS_F32, [0, 1, 3, 0, 0]), (512, S.PS_F64, [0, 1, 1, 0, 0]),
+                          (256, S.PS_F64, [0, 1, 2, 0, 0]),
                           (128, S.PS_F32, [0, 0, 1, 0, 0]), (512, S.PS_F32_SPLIT, [0, 0, 0, 0, 0])]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
         try:
