@@ -126,7 +126,9 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
 
 /* Choose the kernel variant of one pass of a pruned plan (host only, no HIP
  * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = radix-32-
- * based plan (n = 256 and 512 only).  Pass 2 (the fused z pass): 0 =
+ * based plan (n = 256 and 512 only); passes 1 and 3 (the y passes) also
+ * take 2 and 3, the same plans run by persistent workgroups that load the
+ * next tile while transforming the current one.  Pass 2 (the fused z pass): 0 =
  * workgroup-synchronised pencils, 1 = wavefront-owned pencils, 2 =
  * wavefront-owned pencils on the radix-32-based plan (n = 256, 512), 3 = as
  * 2 with persistent workgroups that load the next tile while transforming

@@ -327,6 +327,116 @@ __global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, cons
             gp<const T>(s.ghat), tw_fwd<V, FAM>(s), tw_inv<V, FAM>(s), lds, sa);
 }
 
+// Persistent y passes with a one-tile prefetch: workgroups walk the tiles
+// (same order as the one-tile-per-workgroup grid) and load the next tile's
+// pencils before transforming the current ones.  Column twiddles (every
+// stage but the last) are read from an LDS copy, since a global twiddle
+// load would also wait for the prefetch.
+template <typename V, class RP, int NT> __device__ __forceinline__ void copy_columns(const V* tab, V* dst)
+{
+    constexpr int C = RP::tw_size();
+    const V* col = tab + C;  // columns follow the rows
+    for (int e = threadIdx.x; e < C; e += NT) dst[e] = col[e];
+}
+
+template <typename T, int P, int FAM, int ZT, int NT, int MT>
+__global__ __launch_bounds__(NT) void k_y_fwd_pf(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                                 const unsigned short* __restrict__ stab, int count)
+{
+    using RP = typename PlanFor<P, FAM>::Fwd;
+    using E = Engine<T, RP, ZT, NT, false, MT>;
+    using V = cx<T>;
+    constexpr int N = P / 2, H = N + 1, NZ = (N + ZT - 1) / ZT, C = RP::tw_size() > 0 ? RP::tw_size() : 1;
+    __shared__ V lds[E::LDS_ELEMS];
+    __shared__ V lcol[C];
+    typename E::SA sa;
+    sa.load(stab);
+    const int total = NZ * H * count;
+    int t = blockIdx.x;
+    if (t >= total) return;
+    copy_columns<V, RP, NT>(tw_fwd<V, FAM>(list[0]), lcol);  // made visible by the first stage's barrier
+    auto tile = [&](int u, int& zs, int& kx, int& z0) {
+        zs = u / (NZ * H);
+        const int r = u - zs * (NZ * H);
+        kx = r / NZ;
+        z0 = (r - kx * NZ) * ZT;
+    };
+    auto load = [&](int u, typename E::template Regs<0>& g) {
+        int zs, kx, z0;
+        tile(u, zs, kx, z0);
+        const V* pin = (in ? in : gp<const V>(list[zs].t1)) + ((size_t)kx * N + z0) * N;
+        auto ld = [&](int p, int idx) -> V { return z0 + p < N ? pin[(unsigned)(p * N + idx)] : V{T(0), T(0)}; };
+        E::template load_first<MAP_EF, N>(g, ld);
+    };
+    typename E::template Regs<0> cur;
+    load(t, cur);
+    for (; t < total; t += gridDim.x) {
+        typename E::template Regs<0> nxt;
+        if (t + (int)gridDim.x < total) load(t + gridDim.x, nxt);
+        int zs, kx, z0;
+        tile(t, zs, kx, z0);
+        const SolveRec& s = list[zs];
+        V* pout = (out ? out : gp<V>(s.t2)) + (size_t)kx * P * N + z0;
+        auto st = [&](int p, int idx, V v) {
+            if (z0 + p < N) pout[(unsigned)(idx * N + p)] = v;
+        };
+        E::template run_from_regs<-1, MAP_EF, MAP_EF, MAP_PF, P>(lds, typename E::TW(tw_fwd<V, FAM>(s), lcol), cur,
+                                                                  st, sa);
+        cur = nxt;
+    }
+}
+
+template <typename T, int P, int FAM, int ZT, int NT, int MT>
+__global__ __launch_bounds__(NT) void k_y_inv_pf(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                                 const unsigned short* __restrict__ stab, int count)
+{
+    using RP = typename PlanFor<P, FAM>::Inv;
+    using E = Engine<T, RP, ZT, NT, false, MT>;
+    using V = cx<T>;
+    constexpr int N = P / 2, H = N + 1, HP = t4_pitch(H), NK = (H + ZT - 1) / ZT;
+    constexpr int C = RP::tw_size() > 0 ? RP::tw_size() : 1;
+    __shared__ V lds[E::LDS_ELEMS];
+    __shared__ V lcol[C];
+    typename E::SA sa;
+    sa.load(stab);
+    const int total = NK * N * count;
+    int t = blockIdx.x;
+    if (t >= total) return;
+    copy_columns<V, RP, NT>(tw_inv<V, FAM>(list[0]), lcol);  // made visible by the first stage's barrier
+    // z fastest: consecutive tiles read neighbouring rows of the same 16 kx planes
+    auto tile = [&](int u, int& zs, int& kx0, int& z) {
+        zs = u / (NK * N);
+        const int r = u - zs * (NK * N);
+        kx0 = (r / N) * ZT;
+        z = r - (r / N) * N;
+    };
+    auto load = [&](int u, typename E::template Regs<0>& g) {
+        int zs, kx0, z;
+        tile(u, zs, kx0, z);
+        const V* pin = (in ? in : gp<const V>(list[zs].t3)) + ((size_t)kx0 * N + z) * P;
+        auto ld = [&](int p, int idx) -> V {
+            return kx0 + p < H ? pin[(unsigned)(p * N * P + idx)] : V{T(0), T(0)};
+        };
+        E::template load_first<MAP_EF, P>(g, ld);
+    };
+    typename E::template Regs<0> cur;
+    load(t, cur);
+    for (; t < total; t += gridDim.x) {
+        typename E::template Regs<0> nxt;
+        if (t + (int)gridDim.x < total) load(t + gridDim.x, nxt);
+        int zs, kx0, z;
+        tile(t, zs, kx0, z);
+        const SolveRec& s = list[zs];
+        V* pout = (out ? out : gp<V>(s.t1)) + (size_t)z * N * HP + kx0;
+        auto st = [&](int p, int idx, V v) {
+            if (kx0 + p < H) pout[(unsigned)(idx * HP + p)] = v;
+        };
+        E::template run_from_regs<+1, MAP_EF, MAP_EF, MAP_PF, N>(lds, typename E::TW(tw_inv<V, FAM>(s), lcol), cur,
+                                                                  st, sa);
+        cur = nxt;
+    }
+}
+
 // z_conv, persistent, with a one-tile prefetch (wave-owned pencils).  Each
 // workgroup walks tiles blockIdx.x, + gridDim.x, ... of all `count` solves
 // (the grid is a multiple of 8, so the XCD pairing of z_tile holds).  Per

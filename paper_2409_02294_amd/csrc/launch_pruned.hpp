@@ -20,6 +20,18 @@ constexpr int wave_threads(int B, int P, int E)
     return 64 * (B / ppw);
 }
 
+// Workgroups of `kernel` (nt threads) resident on the device at once, rounded
+// down to a multiple of 8 (the XCD count); a fallback if the query fails.
+template <class K> static int resident_workgroups(K kernel, int nt)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) == hipSuccess && per_cu * cus >= 8)
+        return per_cu * cus / 8 * 8;
+    return 1024;
+}
+
 template <typename T, int P, int FAM, int MT> struct PassLaunch {
     using V = cx<T>;
     static constexpr int N = P / 2, H = N + 1;
@@ -44,27 +56,32 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
         hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H, b.count), dim3(NTZ), 0, b.stream,
                            static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab);
     }
-    // Persistent z pass: as many workgroups as fit on the device at once (a
-    // multiple of 8, so tile pairs stay on one XCD), each walking the tiles.
+    // Persistent passes: as many workgroups as fit on the device at once (a
+    // multiple of 8, so z tile pairs stay on one XCD), each walking tiles.
     static void z_conv_pf(const PrunedBufs& b)
     {
         constexpr int NTZ = wave_threads(ZB, P, E);
-        static int resident = 0;
-        if (resident == 0) {
-            int dev = 0, cus = 0, per_cu = 0;
-            if (hipGetDevice(&dev) == hipSuccess &&
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>, NTZ, 0) ==
-                    hipSuccess &&
-                per_cu * cus >= 8)
-                resident = per_cu * cus / 8 * 8;
-            else
-                resident = 1024;
-        }
+        static const int resident = resident_workgroups(k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>, NTZ);
         const int total = (P / ZB) * H * b.count;
-        const int grid = total < resident ? total : resident;
-        hipLaunchKernelGGL((k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>), dim3(grid), dim3(NTZ), 0, b.stream,
-                           static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab, b.count);
+        hipLaunchKernelGGL((k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>), dim3(total < resident ? total : resident),
+                           dim3(NTZ), 0, b.stream, static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list,
+                           b.stab, b.count);
+    }
+    static void y_fwd_pf(const PrunedBufs& b)
+    {
+        static const int resident = resident_workgroups(k_y_fwd_pf<T, P, FAM, ZT, NTY, MT>, NTY);
+        const int total = ((N + ZT - 1) / ZT) * H * b.count;
+        hipLaunchKernelGGL((k_y_fwd_pf<T, P, FAM, ZT, NTY, MT>), dim3(total < resident ? total : resident), dim3(NTY),
+                           0, b.stream, static_cast<const V*>(b.in[1]), static_cast<V*>(b.out[1]), b.list, b.stab,
+                           b.count);
+    }
+    static void y_inv_pf(const PrunedBufs& b)
+    {
+        static const int resident = resident_workgroups(k_y_inv_pf<T, P, FAM, ZT, NTY, MT>, NTY);
+        const int total = ((H + ZT - 1) / ZT) * N * b.count;
+        hipLaunchKernelGGL((k_y_inv_pf<T, P, FAM, ZT, NTY, MT>), dim3(total < resident ? total : resident), dim3(NTY),
+                           0, b.stream, static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab,
+                           b.count);
     }
     static void y_inv(const PrunedBufs& b)
     {
@@ -91,9 +108,9 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             if (v.x_fam == 1 && F1) L1::x_r2c(b);
             else L0::x_r2c(b);
             break;
-        case 1:
-            if (v.y_fam == 1 && F1) L1::y_fwd(b);
-            else L0::y_fwd(b);
+        case 1:  // variant bit 0: radix-32 family, bit 1: persistent
+            if ((v.y_fam & 1) && F1) (v.y_fam & 2) ? L1::y_fwd_pf(b) : L1::y_fwd(b);
+            else (v.y_fam & 2) ? L0::y_fwd_pf(b) : L0::y_fwd(b);
             break;
         case 2:
             if constexpr (F1) {
@@ -107,8 +124,8 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else L0::template z_conv<false>(b);
             break;
         case 3:
-            if (v.yi_fam == 1 && F1) L1::y_inv(b);
-            else L0::y_inv(b);
+            if ((v.yi_fam & 1) && F1) (v.yi_fam & 2) ? L1::y_inv_pf(b) : L1::y_inv(b);
+            else (v.yi_fam & 2) ? L0::y_inv_pf(b) : L0::y_inv(b);
             break;
         case 4:
             if (v.xc_fam == 1 && F1) L1::x_c2r(b);

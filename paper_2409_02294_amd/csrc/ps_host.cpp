@@ -267,7 +267,11 @@ const char* prec_name(ps_precision p)
     return "?";
 }
 
-int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : 2; }
+int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 4 : 2; }
+
+// Whether variant v of a pass runs the radix-32-based plan family.
+bool variant_needs_family1(int pass, int v) { return pass == 2 ? v >= 2 : (v & 1) != 0; }
+bool family1_available(ps_plan p) { return ps::has_family1(p->P) && p->prec != PS_F32_SPLIT; }
 
 // Runs passes [lo, hi) of a pruned plan's pipeline with its arithmetic.
 hipError_t run_pruned(ps_precision prec, int P, int lo, int hi, const ps::PrunedBufs& b)
@@ -402,8 +406,9 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     // Default variants, as measured fastest per pass on MI355X: wave-owned
     // z pass; where the radix-32-based family exists (P = 512, 1024) it wins
     // for the forward y pass and, in FP32, the z pass (its persistent,
-    // prefetching form), while the x passes and the inverse y pass keep the
-    // radix-16-based family.  Split plans keep the radix-16 stages (their
+    // prefetching form), while the x passes keep the radix-16-based family;
+    // at P = 1024 the inverse y pass runs persistent (radix-32 family in
+    // FP32, radix-16 in FP64).  Split plans keep the radix-16 stages (their
     // matrix-core DFT-16); at P = 1024 their workgroup-synchronised z pass is
     // faster.
     if (prec == PS_F32_SPLIT) {
@@ -412,6 +417,7 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     } else if (ps::has_family1(p->P)) {
         p->var.y_fam = 1;
         p->var.zmode = prec == PS_F64 ? (p->P >= 1024 ? 1 : 2) : 3;
+        if (p->P >= 1024) p->var.yi_fam = prec == PS_F64 ? 2 : 3;  // persistent inverse y pass
     } else {
         p->var.zmode = 1;
     }
@@ -590,8 +596,7 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
     }
     if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..5");
     if (variant < 0 || variant >= num_variants(pass)) return fail(PS_ERR_INVALID, "variant out of range");
-    const bool needs_f1 = (pass == 2) ? variant == 2 : variant == 1;
-    if (needs_f1 && (!ps::has_family1(p->P) || p->prec == PS_F32_SPLIT))
+    if (variant_needs_family1(pass, variant) && !family1_available(p))
         return fail(PS_ERR_UNSUPPORTED, "this plan has no radix-32 plan family");
     *variant_slot(p->var, pass) = variant;
     return PS_OK;
@@ -620,8 +625,7 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
     for (int pass = 0; pass < 5 && rc == PS_OK; ++pass) {
         float best_ms = 1e30f;
         for (int v = 0; v < num_variants(pass); ++v) {
-            const bool needs_f1 = (pass == 2) ? v == 2 : v == 1;
-            if (needs_f1 && (!ps::has_family1(p->P) || p->prec == PS_F32_SPLIT)) continue;
+            if (variant_needs_family1(pass, v) && !family1_available(p)) continue;
             *variant_slot(b.var, pass) = v;
             const int reps = 5;
             float ms = 0.f;

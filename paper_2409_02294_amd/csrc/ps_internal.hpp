@@ -14,7 +14,8 @@ namespace ps {
 
 // Kernel variants of the pruned pipeline (chosen per plan, e.g. by the
 // autotuner).  fam: radix-plan family (0: radix-16 based, 1: radix-32 based
-// where P allows it, else 0).  zmode: 0 workgroup-synchronised z pass,
+// where P allows it, else 0); for the y passes bit 1 (value 2, 3) selects
+// the persistent form with a one-tile prefetch.  zmode: 0 workgroup-synchronised z pass,
 // 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1),
 // 3 persistent wave-owned pencils with a one-tile prefetch (family 1).
 struct PrunedVariant {

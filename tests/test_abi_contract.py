@@ -175,7 +175,7 @@ def test_tuning_cache_is_read(tmp_path):
         assert S.ps_plan_query(p)["variant"] == [0, 1, 3, 0, 0]
     finally:
         S.ps_plan_destroy(p)
-    for n, prec, want in [(512, S.PS_F32, [0, 1, 3, 0, 0]), (512, S.PS_F64, [0, 1, 1, 0, 0]),
+    for n, prec, want in [(512, S.PS_F32, [0, 1, 3, 3, 0]), (512, S.PS_F64, [0, 1, 1, 2, 0]),
                           (256, S.PS_F64, [0, 1, 2, 0, 0]),
                           (128, S.PS_F32, [0, 0, 1, 0, 0]), (512, S.PS_F32_SPLIT, [0, 0, 0, 0, 0])]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
