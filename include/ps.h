@@ -130,9 +130,10 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * take 2 and 3, the same plans run by persistent workgroups that load the
  * next tile while transforming the current one.  Pass 2 (the fused z pass): 0 =
  * workgroup-synchronised pencils, 1 = wavefront-owned pencils, 2 =
- * wavefront-owned pencils on the radix-32-based plan (n = 256, 512), 3 = as
- * 2 with persistent workgroups that load the next tile while transforming
- * the current one (n = 256, 512); 2 and 3 fall back to 1 at other n.  Every
+ * wavefront-owned pencils on the radix-32-based plan (n = 256, 512; else
+ * as 1), 3 = persistent workgroups that load the next tile while
+ * transforming the current one (radix-32-based plan where it exists, else
+ * radix-16-based; not for PS_F32_SPLIT plans).  Every
  * variant computes the same result to rounding.  PS_F32_SPLIT plans keep the
  * radix-16-based plan (variants 0 and 0/1 only); for them "pass" 5 sets the
  * number of split-bf16 product terms per DFT-16: 6 (three pieces per

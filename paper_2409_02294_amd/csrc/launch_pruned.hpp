@@ -60,7 +60,9 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     // multiple of 8, so z tile pairs stay on one XCD), each walking tiles.
     static void z_conv_pf(const PrunedBufs& b)
     {
-        constexpr int NTZ = wave_threads(ZB, P, E);
+        // two or more pencils per wavefront (32 elements per lane): room in
+        // registers for the prefetched tile
+        constexpr int NTZ = wave_threads(ZB, P, 32);
         static const int resident = resident_workgroups(k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>, NTZ);
         const int total = (P / ZB) * H * b.count;
         hipLaunchKernelGGL((k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>), dim3(total < resident ? total : resident),
@@ -113,8 +115,8 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else (v.y_fam & 2) ? L0::y_fwd_pf(b) : L0::y_fwd(b);
             break;
         case 2:
-            if constexpr (F1) {
-                if (v.zmode == 3) {
+            if constexpr (MT == 0 && PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1) {
+                if (v.zmode == 3) {  // persistent: radix-32 family where it exists
                     L1::z_conv_pf(b);
                     break;
                 }

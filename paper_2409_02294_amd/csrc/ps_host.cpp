@@ -270,7 +270,7 @@ const char* prec_name(ps_precision p)
 int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 4 : 2; }
 
 // Whether variant v of a pass runs the radix-32-based plan family.
-bool variant_needs_family1(int pass, int v) { return pass == 2 ? v >= 2 : (v & 1) != 0; }
+bool variant_needs_family1(int pass, int v) { return pass == 2 ? v == 2 : (v & 1) != 0; }
 bool family1_available(ps_plan p) { return ps::has_family1(p->P) && p->prec != PS_F32_SPLIT; }
 
 // Runs passes [lo, hi) of a pruned plan's pipeline with its arithmetic.
@@ -598,6 +598,8 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
     if (variant < 0 || variant >= num_variants(pass)) return fail(PS_ERR_INVALID, "variant out of range");
     if (variant_needs_family1(pass, variant) && !family1_available(p))
         return fail(PS_ERR_UNSUPPORTED, "this plan has no radix-32 plan family");
+    if (pass == 2 && variant == 3 && p->prec == PS_F32_SPLIT)
+        return fail(PS_ERR_UNSUPPORTED, "split plans have no persistent z pass");
     *variant_slot(p->var, pass) = variant;
     return PS_OK;
 }
@@ -626,6 +628,7 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
         float best_ms = 1e30f;
         for (int v = 0; v < num_variants(pass); ++v) {
             if (variant_needs_family1(pass, v) && !family1_available(p)) continue;
+            if (pass == 2 && v == 3 && p->prec == PS_F32_SPLIT) continue;
             *variant_slot(b.var, pass) = v;
             const int reps = 5;
             float ms = 0.f;

@@ -17,7 +17,8 @@ namespace ps {
 // where P allows it, else 0); for the y passes bit 1 (value 2, 3) selects
 // the persistent form with a one-tile prefetch.  zmode: 0 workgroup-synchronised z pass,
 // 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1),
-// 3 persistent wave-owned pencils with a one-tile prefetch (family 1).
+// 3 persistent wave-owned pencils with a one-tile prefetch (family 1 where
+// it exists, else family 0; not for split plans).
 struct PrunedVariant {
     int x_fam = 0, y_fam = 0, zmode = 0, yi_fam = 0, xc_fam = 0;
     int mterms = 0;  // 0: vector-ALU DFTs; 3 or 6: split-bf16 matrix-core radix-16 DFTs (float only)

@@ -148,6 +148,10 @@ def test_variant_selection_contract():
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED  # no radix-32 family at P = 64
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
+        assert lib.ps_plan_set_variant(p, 3, 3) == S.PS_ERR_UNSUPPORTED  # persistent, radix-32 family
+        assert lib.ps_plan_set_variant(p, 3, 2) == S.PS_OK               # persistent, radix-16 family
+        assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_OK               # persistent z pass, radix-16 family
+        S.ps_plan_set_variant(p, 3, 0)
         S.ps_plan_set_variant(p, 2, 0)
         assert S.ps_plan_query(p)["variant"][2] == 0
         S.ps_plan_set_variant(q, 0, 1)
@@ -195,6 +199,7 @@ def test_split_plan_contract():
         assert lib.ps_plan_set_variant(p, 5, 4) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # keeps the radix-16 family
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
+        assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_UNSUPPORTED   # no persistent split z pass
         S.ps_plan_set_variant(p, 5, 3)
         assert S.ps_plan_query(p)["split_terms"] == 3
         assert S.ps_plan_workspace_bytes(p) >= S.ps_plan_workspace_bytes(S.ps_plan_create(256, 1.0 / 256, S.PS_F32))

@@ -297,7 +297,7 @@ def test_variants_agree_n256(prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n", [16, 48, 96])
-@pytest.mark.parametrize("zmode", [0, 1])
+@pytest.mark.parametrize("zmode", [0, 1, 3])
 def test_zmodes_match_oracle(prec, n, zmode):
     rho = inputs.make_density(n, 5, 500 + n, sigma=(0.03, 0.1), noise=1e-3)
     s = S.Solver(n, 1.0 / n, prec)
