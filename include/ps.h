@@ -111,7 +111,11 @@ ps_status ps_solve(ps_plan p, const void *d_rho, void *d_phi, void *stream);
 /* count (1..1024) independent solves enqueued on `stream`.  Members are
  * grouped by length and kernel variant; each pass is one launch per group,
  * over the group's members (grid z), with the same kernels ps_solve uses, so
- * a member's result equals ps_solve's for its plan bitwise.  All plans must
+ * a member's result equals ps_solve's for its plan bitwise.  The groups of a
+ * pass run side by side: the first on `stream`, the others on streams that
+ * plans[0] creates (default priority) and keeps until it is destroyed,
+ * forked from and joined back into `stream` with events, so the batch is
+ * ordered on `stream` as a whole.  All plans must
  * share one pruned precision (PS_F64, PS_F32 or PS_F32_SPLIT); each plan
  * appears at most once and must be built; rho[i] and phi[i] follow the
  * layout of ps_solve, and no output may overlap another array of the batch.
@@ -133,7 +137,9 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * wavefront-owned pencils on the radix-32-based plan (n = 256, 512; else
  * as 1), 3 = persistent workgroups that load the next tile while
  * transforming the current one (radix-32-based plan where it exists, else
- * radix-16-based; not for PS_F32_SPLIT plans).  Every
+ * radix-16-based; not for PS_F32_SPLIT plans), 4 = persistent on the
+ * radix-16-based plan with fewer pencils per wavefront (not for
+ * PS_F32_SPLIT plans).  Every
  * variant computes the same result to rounding.  PS_F32_SPLIT plans keep the
  * radix-16-based plan (variants 0 and 0/1 only); for them "pass" 5 sets the
  * number of split-bf16 product terms per DFT-16: 6 (three pieces per

@@ -58,11 +58,11 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     }
     // Persistent passes: as many workgroups as fit on the device at once (a
     // multiple of 8, so z tile pairs stay on one XCD), each walking tiles.
-    static void z_conv_pf(const PrunedBufs& b)
+    // EL: elements per lane that set the pencils per wavefront (32: two or
+    // more 1024-point pencils per wavefront, 16: one).
+    template <int EL> static void z_conv_pf(const PrunedBufs& b)
     {
-        // two or more pencils per wavefront (32 elements per lane): room in
-        // registers for the prefetched tile
-        constexpr int NTZ = wave_threads(ZB, P, 32);
+        constexpr int NTZ = wave_threads(ZB, P, EL);
         static const int resident = resident_workgroups(k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>, NTZ);
         const int total = (P / ZB) * H * b.count;
         hipLaunchKernelGGL((k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>), dim3(total < resident ? total : resident),
@@ -117,7 +117,13 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
         case 2:
             if constexpr (MT == 0 && PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1) {
                 if (v.zmode == 3) {  // persistent: radix-32 family where it exists
-                    L1::z_conv_pf(b);
+                    L1::template z_conv_pf<32>(b);
+                    break;
+                }
+            }
+            if constexpr (MT == 0 && PlanFor<P, 0>::Fwd::S > 1) {
+                if (v.zmode == 4) {  // persistent: radix-16 family, one 1024-point pencil per wavefront
+                    L0::template z_conv_pf<16>(b);
                     break;
                 }
             }

@@ -17,6 +17,7 @@
 #include <fstream>
 #include <sstream>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ps_internal.hpp"
@@ -210,10 +211,21 @@ struct ps_plan_s {
     size_t off_batch = 0;                   // solve records of a batch this plan leads
     size_t ws_bytes = 0;
     std::vector<uintptr_t> batch_sig;       // batch whose records are in the workspace
+    // streams and events that run a led batch's groups side by side
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
     // bound state
     unsigned char* ws = nullptr;
     bool ready = false;
     double G = 1.0, self_coeff = 2.38;
+
+    ~ps_plan_s()
+    {
+        for (hipStream_t s : aux) (void)hipStreamDestroy(s);
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 namespace {
@@ -598,7 +610,7 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
     if (variant < 0 || variant >= num_variants(pass)) return fail(PS_ERR_INVALID, "variant out of range");
     if (variant_needs_family1(pass, variant) && !family1_available(p))
         return fail(PS_ERR_UNSUPPORTED, "this plan has no radix-32 plan family");
-    if (pass == 2 && variant == 3 && p->prec == PS_F32_SPLIT)
+    if (pass == 2 && variant >= 3 && p->prec == PS_F32_SPLIT)
         return fail(PS_ERR_UNSUPPORTED, "split plans have no persistent z pass");
     *variant_slot(p->var, pass) = variant;
     return PS_OK;
@@ -628,7 +640,7 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
         float best_ms = 1e30f;
         for (int v = 0; v < num_variants(pass); ++v) {
             if (variant_needs_family1(pass, v) && !family1_available(p)) continue;
-            if (pass == 2 && v == 3 && p->prec == PS_F32_SPLIT) continue;
+            if (pass == 2 && v >= 3 && p->prec == PS_F32_SPLIT) continue;
             *variant_slot(b.var, pass) = v;
             const int reps = 5;
             float ms = 0.f;
@@ -713,6 +725,25 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
         for (int x : vkey(i)) sig.push_back((uintptr_t)(intptr_t)x);
     }
     auto* dlist = reinterpret_cast<ps::SolveRec*>(head->ws + head->off_batch);
+    // per pass, runs [k0, k1) of equal length and equal kernel variant
+    std::vector<std::pair<int, int>> groups[5];
+    size_t most = 1;
+    for (int pass = 0; pass < 5; ++pass) {
+        for (int k0 = 0; k0 < count;) {
+            ps::PrunedVariant v0 = plans[order[k0]]->var;
+            int k1 = k0 + 1;
+            while (k1 < count) {
+                ps::PrunedVariant v1 = plans[order[k1]]->var;
+                if (plans[order[k1]]->P != plans[order[k0]]->P ||
+                    *variant_slot(v1, pass) != *variant_slot(v0, pass) || v1.mterms != v0.mterms)
+                    break;
+                ++k1;
+            }
+            groups[pass].emplace_back(k0, k1);
+            k0 = k1;
+        }
+        most = std::max(most, groups[pass].size());
+    }
     if (sig != head->batch_sig) {
         bool cap = false;
         hipError_t e;
@@ -723,27 +754,40 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
         e = hipMemcpyAsync(dlist, recs.data(), recs.size() * sizeof(ps::SolveRec), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host array is released on return
         if (e != hipSuccess) return device_fail(e, "batch record upload");
+        // groups of one pass run side by side: one extra stream per group beyond the first
+        if (most > 1 && !head->fork) {
+            if ((e = hipEventCreateWithFlags(&head->fork, hipEventDisableTiming)) != hipSuccess)
+                return device_fail(e, "hipEventCreateWithFlags");
+        }
+        while (head->aux.size() + 1 < most) {
+            hipStream_t s2 = nullptr;
+            hipEvent_t e2 = nullptr;
+            if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess)
+                return device_fail(e, "hipStreamCreateWithFlags");
+            head->aux.push_back(s2);
+            if ((e = hipEventCreateWithFlags(&e2, hipEventDisableTiming)) != hipSuccess)
+                return device_fail(e, "hipEventCreateWithFlags");
+            head->join.push_back(e2);
+        }
         head->batch_sig = sig;
     }
     for (int pass = 0; pass < 5; ++pass) {
-        for (int k0 = 0; k0 < count;) {
-            const ps_plan p0 = plans[order[k0]];
-            ps::PrunedVariant v0 = p0->var;
-            int k1 = k0 + 1;
-            while (k1 < count) {
-                ps::PrunedVariant v1 = plans[order[k1]]->var;
-                if (plans[order[k1]]->P != p0->P || *variant_slot(v1, pass) != *variant_slot(v0, pass) ||
-                    v1.mterms != v0.mterms)
-                    break;
-                ++k1;
-            }
-            ps::PrunedBufs b = pruned_bufs(p0, nullptr, nullptr, st);
-            b.list = dlist + k0;
-            b.count = k1 - k0;
-            const hipError_t e = run_pruned(prec, p0->P, pass, pass + 1, b);
-            if (e != hipSuccess) return device_fail(e, "batched launch");
-            k0 = k1;
+        const auto& gr = groups[pass];
+        hipError_t e = hipSuccess;
+        if (gr.size() > 1) e = hipEventRecord(head->fork, st);
+        for (size_t g = 0; g < gr.size() && e == hipSuccess; ++g) {
+            hipStream_t sg = g == 0 ? st : head->aux[g - 1];
+            if (g > 0) e = hipStreamWaitEvent(sg, head->fork, 0);
+            if (e != hipSuccess) break;
+            const ps_plan p0 = plans[order[gr[g].first]];
+            ps::PrunedBufs b = pruned_bufs(p0, nullptr, nullptr, sg);
+            b.list = dlist + gr[g].first;
+            b.count = gr[g].second - gr[g].first;
+            e = run_pruned(prec, p0->P, pass, pass + 1, b);
+            if (e == hipSuccess && g > 0) e = hipEventRecord(head->join[g - 1], sg);
         }
+        for (size_t g = 1; g < gr.size() && e == hipSuccess; ++g) e = hipStreamWaitEvent(st, head->join[g - 1], 0);
+        if (e != hipSuccess) return device_fail(e, "batched launch");
     }
     return PS_OK;
 }

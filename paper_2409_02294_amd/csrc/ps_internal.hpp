@@ -18,12 +18,13 @@ namespace ps {
 // the persistent form with a one-tile prefetch.  zmode: 0 workgroup-synchronised z pass,
 // 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1),
 // 3 persistent wave-owned pencils with a one-tile prefetch (family 1 where
-// it exists, else family 0; not for split plans).
+// it exists, else family 0; not for split plans), 4 the same on family 0
+// with fewer pencils per wavefront (one at P = 1024).
 struct PrunedVariant {
     int x_fam = 0, y_fam = 0, zmode = 0, yi_fam = 0, xc_fam = 0;
     int mterms = 0;  // 0: vector-ALU DFTs; 3 or 6: split-bf16 matrix-core radix-16 DFTs (float only)
 };
-constexpr int NUM_ZMODES = 4;
+constexpr int NUM_ZMODES = 5;
 
 // Launch arguments of the pruned pipeline: `count` equal-length solves whose
 // records are the device array `list` (grid z indexes it).  in[k] / out[k],

@@ -144,7 +144,7 @@ def test_variant_selection_contract():
         lib = S.load()
         assert lib.ps_plan_set_variant(p, 6, 0) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 5, 6) == S.PS_ERR_UNSUPPORTED  # product terms: split plans only
-        assert lib.ps_plan_set_variant(p, 2, 4) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 2, 5) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED  # no radix-32 family at P = 64
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
@@ -200,6 +200,7 @@ def test_split_plan_contract():
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # keeps the radix-16 family
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
         assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_UNSUPPORTED   # no persistent split z pass
+        assert lib.ps_plan_set_variant(p, 2, 4) == S.PS_ERR_UNSUPPORTED
         S.ps_plan_set_variant(p, 5, 3)
         assert S.ps_plan_query(p)["split_terms"] == 3
         assert S.ps_plan_workspace_bytes(p) >= S.ps_plan_workspace_bytes(S.ps_plan_create(256, 1.0 / 256, S.PS_F32))

@@ -182,3 +182,55 @@ def test_capture_of_new_batch_is_refused():
             except S.PSError as e:
                 status = e.status
     assert status == S.PS_ERR_CAPTURE
+
+
+# ---------------------------------------------------------------------------
+# The two batched workloads themselves, member by member against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32_split", "f32"])
+def test_batched_workload_matches_oracle(prec):
+    # 96 solves, N in {32, 48, 64, 96, 128} (seeded), 4-32 blobs each, one batched call
+    dens = inputs.batched_workload(96, 4000)
+    solvers = [S.Solver(d.shape[0], 1.0 / d.shape[0], prec) for d in dens]
+    rhos = [torch.from_numpy(d).to("cuda", torch.float32) for d in dens]
+    outs = S.solve_batched(solvers, rhos)
+    torch.cuda.synchronize()
+    worst_l2 = worst_max = 0.0
+    for s, r, o in zip(solvers, rhos, outs):
+        rho64 = r.double().cpu().numpy()
+        ref = oracle.fft_conv(rho64, 1.0 / s.n)
+        got = o.double().cpu().numpy()
+        l2, mx = oracle.rel_l2(got, ref), oracle.rel_max(got, ref)
+        assert l2 <= 1e-6, (s.n, l2)
+        worst_l2, worst_max = max(worst_l2, l2), max(worst_max, mx)
+    print(f"batched workload {prec}: worst member relL2 {worst_l2:.2e}, relMax {worst_max:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["f32_split", "f32"])
+def test_nested_workload_steps(prec):
+    # 384^3 coarse level + two 128^3 levels refined by 2, drifting blobs: steps 0 and 199
+    geometry, sets = inputs.nested_workload(200)
+    solvers = [S.Solver(n, dx, prec) for (n, dx, _) in geometry]
+    for t in (0, 199):
+        dens = [inputs.blob_density(n, sets[t], dx, origin) for (n, dx, origin) in geometry]
+        rhos = [torch.from_numpy(d).to("cuda", torch.float32) for d in dens]
+        outs = S.solve_batched(solvers, rhos)
+        torch.cuda.synchronize()
+        for lv, ((n, dx, _), r, o) in enumerate(zip(geometry, rhos, outs)):
+            rho64 = r.double().cpu().numpy()
+            if n <= 128:
+                ref = oracle.fft_conv(rho64, dx)
+                l2 = oracle.rel_l2(o.double().cpu().numpy(), ref)
+                print(f"nested {prec} step {t} level {lv} ({n}^3): relL2 {l2:.2e}", flush=True)
+                assert l2 <= 1e-6
+            else:
+                rng = np.random.default_rng(t)
+                cells = rng.integers(0, n, (24, 3))
+                cells[:2] = [[n // 2, n // 2, n // 2], [0, n - 1, n // 3]]
+                ref = oracle.direct_sum_cells(rho64, cells, dx)
+                idx = torch.from_numpy(cells).to("cuda", torch.long)
+                got = o[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+                err = float(np.abs(got - ref).max() / np.abs(ref).max())
+                print(f"nested {prec} step {t} level {lv} ({n}^3): sampled relMax {err:.2e}", flush=True)
+                assert err <= 1e-6

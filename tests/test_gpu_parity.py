@@ -203,7 +203,7 @@ def test_n128_full_oracle(prec):
     assert l2 <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f64_plain", "f32_split"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f64_plain", "f32_plain", "f32_split"])
 def test_blobs256_sampled_direct_sum(prec):
     rho = inputs.workload_density("blobs256")
     got, rho_used, _ = gpu_solve(rho, prec)
@@ -276,7 +276,7 @@ def test_variants_agree_n256(prec):
         S.ps_plan_set_variant(s.plan, k, 0)
     base = s(rho).double().cpu().numpy()
     tol = 1e-13 if prec == "f64" else 5e-7
-    for k, nv in zip(range(5), (2, 4, 4, 4, 2)):
+    for k, nv in zip(range(5), (2, 4, 5, 4, 2)):
         for v in range(1, nv):
             S.ps_plan_set_variant(s.plan, k, v)
             got = s(rho).double().cpu().numpy()
@@ -297,7 +297,7 @@ def test_variants_agree_n256(prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n", [16, 48, 96])
-@pytest.mark.parametrize("zmode", [0, 1, 3])
+@pytest.mark.parametrize("zmode", [0, 1, 3, 4])
 def test_zmodes_match_oracle(prec, n, zmode):
     rho = inputs.make_density(n, 5, 500 + n, sigma=(0.03, 0.1), noise=1e-3)
     s = S.Solver(n, 1.0 / n, prec)
