@@ -177,7 +177,8 @@ def _time_replays(torch, g, steps, warmup):
 
 def batched_leg(torch, S, prec, steps, warmup):
     """96 independent solves of sizes drawn from {32, 48, 64, 96, 128} as one
-    batched solve (five grouped launches), replayed from a captured graph."""
+    batched solve (per pass one launch per size group, groups side by side),
+    replayed from a captured graph."""
     import numpy as np
     from paper_2409_02294_amd import inputs
     dens = inputs.batched_workload(96, 4000)
@@ -186,7 +187,7 @@ def batched_leg(torch, S, prec, steps, warmup):
     solvers = [S.Solver(n, 1.0 / n, prec) for n in sizes]
     rhos = [torch.from_numpy(d).to("cuda", dt) for d in dens]
     outs = [torch.empty_like(r) for r in rhos]
-    S.solve_batched(solvers, rhos, outs)  # first call: uploads the work list
+    S.solve_batched(solvers, rhos, outs)  # first call: uploads the member records
     torch.cuda.synchronize()
     g = _graph_of(torch, lambda: S.solve_batched(solvers, rhos, outs))
     ms = _time_replays(torch, g, steps, warmup)
@@ -203,7 +204,7 @@ def batched_leg(torch, S, prec, steps, warmup):
     rb = 8 if prec == "f64" else 4
     b2 = sum(model_bytes(n, rb)["B2"] for n in sizes)
     hist = {str(n): sizes.count(n) for n in sorted(set(sizes))}
-    return {"workload": "96 solves, N in {32,48,64,96,128} (seeded), 4-32 blobs each, one batched solve (5 grouped launches), "
+    return {"workload": "96 solves, N in {32,48,64,96,128} (seeded), 4-32 blobs each, one batched solve (per pass one launch per size group), "
                         "replayed from a captured graph",
             "precision": prec, "sizes": hist, "ms_per_batch": ms, "solves_per_s": 96.0 / (ms * 1e-3),
             "B2_bytes_per_batch": b2, "effective_GBps_B2": b2 / (ms * 1e-3) / 1e9,
@@ -227,7 +228,7 @@ def nested_leg(torch, S, prec, nsteps, warmup):
             inputs.blob_density_torch(n, blobs, dx, origin, out=dens[lv][t])
     rin = [torch.empty((n, n, n), dtype=dt, device="cuda") for (n, _, _) in geometry]
     outs = [torch.empty_like(r) for r in rin]
-    S.solve_batched(solvers, rin, outs)  # uploads the (fixed) work list
+    S.solve_batched(solvers, rin, outs)  # uploads the (fixed) member records
     torch.cuda.synchronize()
 
     def step(t):

@@ -545,7 +545,7 @@ ps_status ps_green_build(ps_plan p, void* d_workspace, double G, double self_coe
     p->G = G;
     p->self_coeff = self_coeff;
     p->ready = true;
-    p->batch_sig.clear();  // a rebuilt plan invalidates any uploaded work list
+    p->batch_sig.clear();  // a rebuilt plan invalidates any uploaded batch records
     return PS_OK;
 }
 

@@ -225,7 +225,7 @@ class Solver:
 
 
 def solve_batched(solvers: List[Solver], rhos, outs=None):
-    """One batched solve (five grouped launches) over several solvers' densities."""
+    """One batched solve (ps_solve_batched) over several solvers' densities."""
     import torch
     if outs is None:
         outs = [torch.empty_like(r) for r in rhos]

@@ -95,7 +95,7 @@ def test_batch_repeat_and_reorder():
     again = S.solve_batched(solvers, rhos)  # same list: no upload
     for a, b in zip(first, again):
         assert torch.equal(a, b)
-    # a different order is a different batch (new work list)
+    # a different order is a different batch (new member records)
     rev = S.solve_batched(solvers[::-1], rhos[::-1])
     for a, b in zip(first, rev[::-1]):
         assert torch.equal(a, b)
@@ -153,7 +153,7 @@ def test_graph_replay_batched():
     sizes = [32, 48, 64, 96, 128, 32, 64]
     solvers, rhos = _make("f32", sizes, 4400)
     outs = [torch.empty_like(r) for r in rhos]
-    S.solve_batched(solvers, rhos, outs)  # first call uploads the work list
+    S.solve_batched(solvers, rhos, outs)  # first call uploads the member records
     torch.cuda.synchronize()
     eager = [o.clone() for o in outs]
     stream = torch.cuda.Stream()
