@@ -319,6 +319,62 @@ def nested_leg(torch, S, prec, nsteps, warmup):
             "max_rel_l2_vs_single_solves": worst}
 
 
+def host_leg(torch, S, prec="f32", n=256, count=16):
+    """Host-resident densities (the paper's section 2.2 topic): 128^3 transfer
+    times from pinned and pageable host memory, and `count` solves at n^3 run
+    by ps_solve_host (uploads and downloads overlapping the solves) against a
+    serial copy-in / solve / copy-out loop.  All rates include PCIe."""
+    dt = torch.float64 if prec.startswith("f64") else torch.float32
+
+    def timed(fn, reps=3, warm=3):
+        # the first host-memory transfers of fresh pinned arrays run slower
+        # (page mapping); time the steady state
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    out = {"precision": prec}
+    small = torch.rand((128,) * 3, dtype=dt)
+    dev = torch.empty_like(small, device="cuda")
+    for kind, host in (("pinned", small.pin_memory()), ("pageable", small)):
+        out[f"h2d_128_ms_{kind}"] = timed(lambda: dev.copy_(host, non_blocking=True), 10) * 1e3
+        out[f"d2h_128_ms_{kind}"] = timed(lambda: host.copy_(dev, non_blocking=True), 10) * 1e3
+    s = S.Solver(n, 1.0 / n, prec)
+    stage = torch.empty(S.ps_host_stage_bytes(s.plan), dtype=torch.uint8, device="cuda")
+    rho_p = [torch.rand((n,) * 3, dtype=dt).pin_memory() for _ in range(count)]
+    phi_p = [torch.empty_like(r).pin_memory() for r in rho_p]
+    rho_g = [r.clone() for r in rho_p]
+    phi_g = [torch.empty_like(r) for r in rho_g]
+    t_pipe = timed(lambda: s.solve_host(rho_p, phi_p, stage))
+    t_page = timed(lambda: s.solve_host(rho_g, phi_g, stage))
+    d_rho = torch.empty((n,) * 3, dtype=dt, device="cuda")
+    d_phi = torch.empty_like(d_rho)
+
+    def serial():
+        for r, o in zip(rho_p, phi_p):
+            d_rho.copy_(r, non_blocking=True)
+            s(d_rho, d_phi)
+            o.copy_(d_phi, non_blocking=True)
+    t_ser = timed(serial)
+    ok = all(torch.equal(a, b) for a, b in zip(phi_p, phi_g))
+    out.update({
+        "workload": f"{count} solves at {n}^3 from host memory, one plan, two device staging slots per direction",
+        "solves_per_s_pipelined_pinned": count / t_pipe,
+        "solves_per_s_pipelined_pageable": count / t_page,
+        "solves_per_s_serial_pinned": count / t_ser,
+        "pinned_equals_pageable": ok,
+        "array_MB": n ** 3 * (8 if dt == torch.float64 else 4) / 1e6,
+    })
+    return out
+
+
 def host_cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -493,6 +549,8 @@ def main() -> int:
                     help="turn two rocprofv3 --pmc counter CSVs of a --pass-loop run into "
                          "profiles/hbm_traffic_counters.json")
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-solve batched leg")
+    ap.add_argument("--no-host", action="store_true", help="skip the host-resident (PCIe-inclusive) leg")
+    ap.add_argument("--host-leg-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--nested-steps", type=int, default=200, help="steps of the nested leg (0 skips it)")
     args = ap.parse_args()
 
@@ -514,6 +572,9 @@ def main() -> int:
     n = args.n
     if args.pass_loop:
         return pass_loop(torch, S, args)
+    if args.host_leg_only:
+        print(json.dumps(host_leg(torch, S, args.precision)), flush=True)
+        return 0
     name = {512: "blobs512", 256: "blobs256", 32: "blobs32"}.get(n)
     t0 = time.perf_counter()
     log(f"generating the {n}^3 density")
@@ -669,6 +730,21 @@ def main() -> int:
         log("nested leg")
         out["nested"] = nested_leg(torch, S, side_prec, args.nested_steps, args.warmup)
         torch.cuda.empty_cache()
+
+    if not args.no_host:
+        # HIP multiplexes streams onto GPU_MAX_HW_QUEUES hardware queues; after
+        # the legs above (graph-capture streams, batch streams) the copy
+        # streams would share a queue with the compute stream and serialise,
+        # so this leg runs in a child process with only its own streams.
+        log("host-resident leg (child process)")
+        import subprocess
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--host-leg-only", "--precision", side_prec],
+                           capture_output=True, text=True, timeout=300)
+        if r.returncode == 0:
+            out["host_resident"] = json.loads(r.stdout.strip().splitlines()[-1])
+            out["host_resident"]["process"] = "child process (fresh HIP runtime)"
+        else:
+            out["host_resident"] = {"error": r.stderr.strip()[-500:]}
 
     if not args.no_cpu_baseline:
         import oracle

@@ -108,6 +108,28 @@ ps_status ps_green_build(ps_plan p, void *d_workspace, double G, double self_coe
 /* One solve: phi = potential of rho, enqueued on `stream`. */
 ps_status ps_solve(ps_plan p, const void *d_rho, void *d_phi, void *stream);
 
+/* Bytes of caller-owned device staging memory that ps_solve_host needs for
+ * this plan: two input and two output slots of n^3 reals (256-byte aligned).
+ * Host only, no HIP call. */
+ps_status ps_host_stage_bytes(ps_plan p, size_t *bytes);
+
+/* count solves with one plan on host-resident densities: rho[i] -> phi[i],
+ * host pointers to n^3 reals in the layout of ps_solve.  The host <-> device
+ * copies the paper's section 2.2 measures (pinned against pageable host
+ * memory) are staged through d_stage (at least ps_host_stage_bytes, 256-byte
+ * aligned, two slots per direction) and run on two copy streams that the
+ * plan creates (default priority) and keeps until it is destroyed: the
+ * upload of solve i + 1 and the download of solve i - 1 overlap solve i,
+ * which runs on `stream`.  Overlap needs pinned host memory (hipHostMalloc,
+ * torch pin_memory); with pageable memory the runtime stages each copy and
+ * little overlaps.  Everything is ordered after earlier work on `stream`
+ * and `stream` resumes after the last download; the call returns before the
+ * copies complete, so the host arrays must stay valid until `stream` is
+ * synchronised.  A plan runs one such sequence at a time.  Not under stream
+ * capture (PS_ERR_CAPTURE). */
+ps_status ps_solve_host(ps_plan p, const void *const *h_rho, void *const *h_phi, int count, void *d_stage,
+                        size_t stage_bytes, void *stream);
+
 /* count (1..1024) independent solves enqueued on `stream`.  Members are
  * grouped by length and kernel variant; each pass is one launch per group,
  * over the group's members (grid z), with the same kernels ps_solve uses, so

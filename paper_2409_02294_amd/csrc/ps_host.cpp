@@ -215,6 +215,9 @@ struct ps_plan_s {
     std::vector<hipStream_t> aux;
     std::vector<hipEvent_t> join;
     hipEvent_t fork = nullptr;
+    // copy streams and events of host-resident solves (fork, upload, solve, download x 2 slots)
+    hipStream_t up = nullptr, down = nullptr;
+    hipEvent_t hev[7] = {};
     // bound state
     unsigned char* ws = nullptr;
     bool ready = false;
@@ -225,6 +228,10 @@ struct ps_plan_s {
         for (hipStream_t s : aux) (void)hipStreamDestroy(s);
         for (hipEvent_t e : join) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
+        if (up) (void)hipStreamDestroy(up);
+        if (down) (void)hipStreamDestroy(down);
+        for (hipEvent_t e : hev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -266,6 +273,30 @@ ps::PrunedBufs pruned_bufs(ps_plan p, const void* rho, void* phi, hipStream_t s)
     b.stream = s;
     return b;
 }
+
+hipError_t run_pruned(ps_precision prec, int P, int lo, int hi, const ps::PrunedBufs& b);
+
+// The kernels of one solve, enqueued on `st` (arguments already checked).
+hipError_t enqueue_solve(ps_plan p, const void* d_rho, void* d_phi, hipStream_t st)
+{
+    if (is_plain(p->prec)) {
+        ps::PlainBufs b;
+        b.rho = d_rho;
+        b.phi = d_phi;
+        b.pad = p->ws + p->off_pad;
+        b.spec = p->ws + p->off_spec;
+        b.ghat = p->ws + p->off_ghat;
+        b.twf = p->ws + p->off_tab + p->tw_f;
+        b.twi = p->ws + p->off_tab + p->tw_i;
+        b.stream = st;
+        return is_f64(p->prec) ? ps::plain_run_f64(p->P, b) : ps::plain_run_f32(p->P, b);
+    }
+    const ps::PrunedBufs b = pruned_bufs(p, d_rho, d_phi, st);
+    return run_pruned(p->prec, p->P, 0, 5, b);
+}
+
+// Device staging for host-resident solves: two input and two output slots.
+size_t host_stage_bytes(ps_plan p) { return 4 * align_up((size_t)p->n * p->n * p->n * p->real_bytes); }
 
 const char* prec_name(ps_precision p)
 {
@@ -558,24 +589,77 @@ ps_status ps_solve(ps_plan p, const void* d_rho, void* d_phi, void* stream)
     const size_t bytes = (size_t)p->n * p->n * p->n * p->real_bytes;
     if (overlap(d_rho, bytes, d_phi, bytes)) return fail(PS_ERR_INVALID, "rho and phi overlap");
     if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e;
-    if (is_plain(p->prec)) {
-        ps::PlainBufs b;
-        b.rho = d_rho;
-        b.phi = d_phi;
-        b.pad = p->ws + p->off_pad;
-        b.spec = p->ws + p->off_spec;
-        b.ghat = p->ws + p->off_ghat;
-        b.twf = p->ws + p->off_tab + p->tw_f;
-        b.twi = p->ws + p->off_tab + p->tw_i;
-        b.stream = st;
-        e = is_f64(p->prec) ? ps::plain_run_f64(p->P, b) : ps::plain_run_f32(p->P, b);
-    } else {
-        const ps::PrunedBufs b = pruned_bufs(p, d_rho, d_phi, st);
-        e = run_pruned(p->prec, p->P, 0, 5, b);
-    }
+    const hipError_t e = enqueue_solve(p, d_rho, d_phi, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "solve launch");
+    return PS_OK;
+}
+
+ps_status ps_host_stage_bytes(ps_plan p, size_t* bytes)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    *bytes = host_stage_bytes(p);
+    return PS_OK;
+}
+
+ps_status ps_solve_host(ps_plan p, const void* const* h_rho, void* const* h_phi, int count, void* d_stage,
+                        size_t stage_bytes, void* stream)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (!h_rho || !h_phi) return fail(PS_ERR_INVALID, "rho and phi lists must be non-NULL");
+    if (count <= 0) return fail(PS_ERR_INVALID, "count must be positive");
+    const size_t bytes = (size_t)p->n * p->n * p->n * p->real_bytes;
+    for (int i = 0; i < count; ++i) {
+        if (!h_rho[i] || !h_phi[i]) return fail(PS_ERR_INVALID, "solve " + std::to_string(i) + ": NULL array");
+        if (overlap(h_rho[i], bytes, h_phi[i], bytes))
+            return fail(PS_ERR_INVALID, "solve " + std::to_string(i) + ": rho and phi overlap");
+    }
+    if (!d_stage) return fail(PS_ERR_INVALID, "staging memory is NULL");
+    if ((uintptr_t)d_stage % ALIGN) return fail(PS_ERR_INVALID, "staging memory must be 256-byte aligned");
+    if (stage_bytes < host_stage_bytes(p)) return fail(PS_ERR_INVALID, "staging memory smaller than ps_host_stage_bytes");
+    if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
+    hipStream_t st = (hipStream_t)stream;
+    bool cap = false;
+    hipError_t e;
+    if (!capturing(st, cap, e)) return device_fail(e, "hipStreamIsCapturing");
+    if (cap) return fail(PS_ERR_CAPTURE, "host-resident solves cannot run under stream capture");
+    if (!p->up) {
+        if ((e = hipStreamCreateWithFlags(&p->up, hipStreamNonBlocking)) != hipSuccess)
+            return device_fail(e, "hipStreamCreateWithFlags");
+        if ((e = hipStreamCreateWithFlags(&p->down, hipStreamNonBlocking)) != hipSuccess)
+            return device_fail(e, "hipStreamCreateWithFlags");
+        for (hipEvent_t& ev : p->hev)
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+                return device_fail(e, "hipEventCreateWithFlags");
+    }
+    // two slots per direction: rho[0], rho[1], phi[0], phi[1]
+    unsigned char* stage = static_cast<unsigned char*>(d_stage);
+    const size_t slot = align_up(bytes);
+    auto d_rho = [&](int s2) { return stage + s2 * slot; };
+    auto d_phi = [&](int s2) { return stage + (2 + s2) * slot; };
+    hipEvent_t fork = p->hev[0], *up_done = p->hev + 1, *comp_done = p->hev + 3, *down_done = p->hev + 5;
+    e = hipEventRecord(fork, st);  // the copies follow earlier work on `stream`
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->up, fork, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->down, fork, 0);
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
+        const int s2 = i & 1;
+        // upload i once solve i - 2 has read this input slot
+        if (i >= 2) e = hipStreamWaitEvent(p->up, comp_done[s2], 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_rho(s2), h_rho[i], bytes, hipMemcpyHostToDevice, p->up);
+        if (e == hipSuccess) e = hipEventRecord(up_done[s2], p->up);
+        // solve i once its input is in and download i - 2 has read this output slot
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, up_done[s2], 0);
+        if (e == hipSuccess && i >= 2) e = hipStreamWaitEvent(st, down_done[s2], 0);
+        if (e == hipSuccess) e = enqueue_solve(p, d_rho(s2), d_phi(s2), st);
+        if (e == hipSuccess) e = hipEventRecord(comp_done[s2], st);
+        // download i once solve i is done
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->down, comp_done[s2], 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_phi[i], d_phi(s2), bytes, hipMemcpyDeviceToHost, p->down);
+        if (e == hipSuccess) e = hipEventRecord(down_done[s2], p->down);
+    }
+    // `stream` resumes after the last downloads
+    for (int s2 = 0; s2 < 2 && s2 < count && e == hipSuccess; ++s2) e = hipStreamWaitEvent(st, down_done[s2], 0);
+    if (e != hipSuccess) return device_fail(e, "host-resident solves");
     return PS_OK;
 }
 

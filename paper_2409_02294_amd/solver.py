@@ -39,7 +39,7 @@ SUPPORTED_N = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 EXPORTS = ("ps_plan_create", "ps_plan_workspace_bytes", "ps_plan_query", "ps_green_build", "ps_solve",
            "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass",
-           "ps_plan_set_variant", "ps_autotune")
+           "ps_plan_set_variant", "ps_autotune", "ps_host_stage_bytes", "ps_solve_host")
 
 
 class PSError(RuntimeError):
@@ -80,6 +80,8 @@ def load() -> ctypes.CDLL:
         "ps_green_build": ([vp, vp, d, d, vp], i),
         "ps_solve": ([vp, vp, vp, vp], i),
         "ps_solve_batched": ([ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], i),
+        "ps_host_stage_bytes": ([vp, ctypes.POINTER(sz)], i),
+        "ps_solve_host": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp, sz, vp], i),
         "ps_plan_destroy": ([vp], None),
         "ps_status_str": ([i], ctypes.c_char_p),
         "ps_last_error": ([], ctypes.c_char_p),
@@ -147,6 +149,21 @@ def ps_solve_batched(plans: Sequence[int], rho: Sequence[int], phi: Sequence[int
     _check(load().ps_solve_batched(arr(*plans), n, arr(*rho), arr(*phi), stream), "ps_solve_batched")
 
 
+def ps_host_stage_bytes(plan: int) -> int:
+    v = ctypes.c_size_t()
+    _check(load().ps_host_stage_bytes(plan, ctypes.byref(v)), "ps_host_stage_bytes")
+    return v.value
+
+
+def ps_solve_host(plan: int, rho: Sequence[int], phi: Sequence[int], stage: int, stage_bytes: int,
+                  stream: int) -> None:
+    n = len(rho)
+    if len(phi) != n:
+        raise ValueError("rho and phi must have equal length")
+    arr = ctypes.c_void_p * max(n, 1)
+    _check(load().ps_solve_host(plan, arr(*rho), arr(*phi), n, stage, stage_bytes, stream), "ps_solve_host")
+
+
 def ps_plan_destroy(plan: int) -> None:
     if plan:
         load().ps_plan_destroy(plan)
@@ -192,6 +209,26 @@ class Solver:
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             stream = torch.cuda.current_stream(self.device).cuda_stream
             ps_green_build(self.plan, self.workspace.data_ptr(), G, self_coeff, stream)
+
+    def solve_host(self, rhos, outs=None, stage=None):
+        """Solves of host-resident densities (CPU tensors, pinned for overlap),
+        staged through device memory (ps_solve_host); returns the host outputs
+        once `stream` has them."""
+        torch = self.torch
+        if outs is None:
+            outs = [torch.empty_like(r) for r in rhos]
+        for t in list(rhos) + list(outs):
+            if t.device.type != "cpu" or t.dtype != self.dtype or tuple(t.shape) != (self.n,) * 3 or not t.is_contiguous():
+                raise ValueError(f"host arrays must be contiguous {self.dtype} CPU tensors of shape {(self.n,) * 3}")
+        nbytes = ps_host_stage_bytes(self.plan)
+        if stage is None:
+            stage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device)
+            ps_solve_host(self.plan, [r.data_ptr() for r in rhos], [o.data_ptr() for o in outs], stage.data_ptr(),
+                          stage.numel(), stream.cuda_stream)
+            stream.synchronize()
+        return outs
 
     def info(self) -> Dict:
         return ps_plan_query(self.plan)

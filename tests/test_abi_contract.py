@@ -206,3 +206,30 @@ def test_split_plan_contract():
         assert S.ps_plan_workspace_bytes(p) >= S.ps_plan_workspace_bytes(S.ps_plan_create(256, 1.0 / 256, S.PS_F32))
     finally:
         S.ps_plan_destroy(p)
+
+
+def test_host_solve_contract():
+    # staging size and every argument check of ps_solve_host, before any HIP call
+    lib = S.load()
+    p = S.ps_plan_create(64, 1.0 / 64, S.PS_F32)
+    q = S.ps_plan_create(48, 1.0 / 48, S.PS_F64)
+    try:
+        assert S.ps_host_stage_bytes(p) == 4 * 64 ** 3 * 4
+        assert S.ps_host_stage_bytes(q) == 4 * ((48 ** 3 * 8 + 255) // 256 * 256)
+        vp = ctypes.c_void_p
+        host = [ctypes.create_string_buffer(64 ** 3 * 4) for _ in range(4)]
+        rho = (vp * 2)(ctypes.addressof(host[0]), ctypes.addressof(host[1]))
+        phi = (vp * 2)(ctypes.addressof(host[2]), ctypes.addressof(host[3]))
+        stage, nb = 0x100000, S.ps_host_stage_bytes(p)  # never dereferenced: every case fails first
+        assert lib.ps_solve_host(p, None, phi, 2, stage, nb, None) == S.PS_ERR_INVALID
+        assert lib.ps_solve_host(p, rho, phi, 0, stage, nb, None) == S.PS_ERR_INVALID
+        assert lib.ps_solve_host(p, rho, phi, 2, None, nb, None) == S.PS_ERR_INVALID
+        assert lib.ps_solve_host(p, rho, phi, 2, stage + 8, nb, None) == S.PS_ERR_INVALID  # alignment
+        assert lib.ps_solve_host(p, rho, phi, 2, stage, nb - 1, None) == S.PS_ERR_INVALID  # too small
+        same = (vp * 2)(ctypes.addressof(host[0]), ctypes.addressof(host[1]))
+        assert lib.ps_solve_host(p, rho, same, 2, stage, nb, None) == S.PS_ERR_INVALID    # rho is phi
+        assert lib.ps_solve_host(p, rho, phi, 2, stage, nb, None) == S.PS_ERR_NOT_READY   # no Green's function
+        assert "ps_green_build" in lib.ps_last_error().decode()
+    finally:
+        S.ps_plan_destroy(p)
+        S.ps_plan_destroy(q)
