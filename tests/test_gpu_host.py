@@ -53,3 +53,40 @@ def test_host_solves_repeat_with_other_arrays():
     ob = s.solve_host(b, stage=stage)
     for r, o in zip(a + b, oa + ob):
         assert torch.equal(o, s(r.to("cuda")).cpu())
+
+
+def test_plan_lifecycle_with_streams():
+    # plans that own batch and copy streams are created and destroyed repeatedly
+    for it in range(6):
+        sizes = [32, 48, 64]
+        solvers = [S.Solver(n, 1.0 / n, "f32") for n in sizes]
+        rhos = [d.to("cuda") for d in (_densities(n, 1, 6300 + it * 10 + n, torch.float32)[0] for n in sizes)]
+        outs = S.solve_batched(solvers, rhos)
+        host = [r.cpu().pin_memory() for r in rhos]
+        back = [solvers[k].solve_host([host[k]])[0] for k in range(len(sizes))]
+        for s, r, o, b in zip(solvers, rhos, outs, back):
+            ref = s(r)
+            assert torch.equal(o, ref) and torch.equal(b, ref.cpu())
+        for s in solvers:
+            s.close()
+    torch.cuda.synchronize()
+
+
+def test_two_plans_on_two_streams():
+    # plans own their workspaces: solves of two plans may run concurrently
+    n = 64
+    a, b = S.Solver(n, 1.0 / n, "f32"), S.Solver(n, 1.0 / n, "f64")
+    ra = _densities(n, 1, 6400, torch.float32)[0].to("cuda")
+    rb = _densities(n, 1, 6401, torch.float64)[0].to("cuda")
+    ref_a, ref_b = a(ra), b(rb)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs_a, outs_b = [], []
+    for _ in range(4):
+        with torch.cuda.stream(s1):
+            outs_a.append(a(ra))
+        with torch.cuda.stream(s2):
+            outs_b.append(b(rb))
+    torch.cuda.synchronize()
+    for oa, ob in zip(outs_a, outs_b):
+        assert torch.equal(oa, ref_a) and torch.equal(ob, ref_b)
