@@ -90,6 +90,15 @@ def test_fft_conv_equals_direct_sum_blobs32(oracle_lib):
     assert oracle_lib.rel_max(a, b) <= 1e-13
 
 
+def test_fft_conv_equals_direct_sum_full_64(oracle_lib):
+    # every cell of a 64^3 grid by the definition (6.9e10 pair terms, ~10 s on 8 cores)
+    rho = inputs.make_density(64, 6, 64064, sigma=(0.03, 0.08), noise=1e-3)
+    ref = oracle_lib.direct_sum(rho, 1.0 / 64)
+    phi = oracle_lib.fft_conv(rho, 1.0 / 64)
+    assert oracle_lib.rel_l2(phi, ref) <= 1e-13
+    assert oracle_lib.rel_max(phi, ref) <= 1e-13
+
+
 def test_fft_conv_equals_direct_sum_sampled_64(oracle_lib):
     rho = inputs.make_density(64, 16, 77, sigma=(0.02, 0.06), noise=1e-3)
     phi = oracle_lib.fft_conv(rho, 1.0 / 64)
