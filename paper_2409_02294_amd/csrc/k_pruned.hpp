@@ -13,9 +13,10 @@
 // The zero padding to P is never stored: the first stage of every forward
 // transform treats inputs >= N as zeros, and the last stage of every inverse
 // transform produces only outputs < N (the crop).  Every pass reads whole
-// contiguous pencils and writes its output as rows of 16 interleaved pencils
-// (128 bytes in FP32, 8 pencils in FP64), the access pattern HBM serves best
-// in both directions on MI355X.
+// contiguous pencils (x_c2r: whole rows of T4) and writes its output as rows
+// of 16 interleaved pencils (128 bytes in FP32, 8 pencils in FP64), the
+// access pattern HBM serves best in both directions on MI355X; x_c2r writes
+// the cropped real rows of phi directly.
 //
 // Real transforms along x pack two density rows into one complex pencil
 // (row a + i row b); the two half spectra separate by Hermitian symmetry,
@@ -40,7 +41,8 @@ __host__ __device__ constexpr int t4_pitch(int H) { return (H + 15) / 16 * 16; }
 
 // Each pass is a tile function (one workgroup's share, addressed by tile
 // coordinates, using a caller-provided LDS buffer of at least LDS elements),
-// wrapped below as a one-tile-per-workgroup kernel.
+// wrapped below as a one-tile-per-workgroup kernel; the y and z passes also
+// have persistent kernels that walk the tiles with a one-tile prefetch.
 
 // Element-wise copy of COUNT items src(e) -> dst(e, v) by the NT threads of a
 // workgroup, each thread issuing all its loads before its stores, so a tile
