@@ -60,9 +60,28 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_example()
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources")
+        print(f"built {LIB} from {len(srcs)} sources, and {EXAMPLE}")
     return LIB
+
+
+EXAMPLE = os.path.join(HERE, "examples", "solve_c")
+ROCM = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+
+
+def build_example() -> str:
+    """The plain-C caller of the ABI (examples/solve_c.c), linked against the
+    in-tree libps.so and the HIP runtime (no torch)."""
+    src = EXAMPLE + ".c"
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", src, "-o", EXAMPLE,
+           "-I", os.path.join(os.path.dirname(HERE), "include"), "-I", os.path.join(ROCM, "include"),
+           "-D__HIP_PLATFORM_AMD__", "-L", HERE, "-lps", "-Wl,-rpath,$ORIGIN/..",
+           "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{r.stderr}")
+    return EXAMPLE
 
 
 if __name__ == "__main__":
