@@ -11,8 +11,11 @@
  *
  * by zero-padding rho to P = 2N per axis, a forward real-to-complex 3D FFT,
  * a pointwise product with the pre-transformed kernel, an inverse FFT and a
- * crop back to [0,N)^3.  Supported N: 8, 16, 24, 32, 48, 64, 96, 128, 192,
- * 256, 384, 512 (P = 2N must be 2^a or 3*2^a, 16 <= P <= 1024).
+ * crop back to [0,N)^3.  Supported N: 8 m for m = 1 .. 64 with no prime
+ * factor of m above 5, i.e. P = 2N = 2^a 3^b 5^c with a >= 4 and
+ * 16 <= P <= 1024 (N = 8, 16, 24, 32, 40, 48, 64, 72, 80, 96, 120, 128,
+ * 144, 160, 192, 200, 216, 240, 256, 288, 320, 360, 384, 400, 432, 480,
+ * 512).
  *
  * Memory.  Every pointer passed to the library is a device pointer the
  * caller owns (e.g. torch.Tensor.data_ptr()).  rho and phi are dense

@@ -41,8 +41,7 @@ hipError_t green_run(int P, const GreenBufs& b)
     switch (P) {
 #define PS_CASE(PP) \
     case PP: return green_passes<PP>(b);
-        PS_CASE(16) PS_CASE(32) PS_CASE(48) PS_CASE(64) PS_CASE(96) PS_CASE(128)
-        PS_CASE(192) PS_CASE(256) PS_CASE(384) PS_CASE(512) PS_CASE(768) PS_CASE(1024)
+        PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
     default: return hipErrorInvalidValue;
     }
@@ -62,8 +61,7 @@ bool host_radices(int P, std::vector<int>& fwd, int fam)
     switch (P) {
 #define PS_CASE(PP) \
     case PP: rlist<PlanFor<PP>::Fwd>(fwd); return true;
-        PS_CASE(16) PS_CASE(32) PS_CASE(48) PS_CASE(64) PS_CASE(96) PS_CASE(128)
-        PS_CASE(192) PS_CASE(256) PS_CASE(384) PS_CASE(512) PS_CASE(768) PS_CASE(1024)
+        PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
     default: return false;
     }

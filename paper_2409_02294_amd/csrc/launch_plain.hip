@@ -47,8 +47,7 @@ template <typename T> static hipError_t plain_dispatch(int P, const PlainBufs& b
     switch (P) {
 #define PS_CASE(PP) \
     case PP: return plain_passes<T, PP>(b);
-        PS_CASE(16) PS_CASE(32) PS_CASE(48) PS_CASE(64) PS_CASE(96) PS_CASE(128)
-        PS_CASE(192) PS_CASE(256) PS_CASE(384) PS_CASE(512) PS_CASE(768) PS_CASE(1024)
+        PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
     default: return hipErrorInvalidValue;
     }

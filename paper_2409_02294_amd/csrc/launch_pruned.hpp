@@ -20,6 +20,18 @@ constexpr int wave_threads(int B, int P, int E)
     return 64 * (B / ppw);
 }
 
+// Whether the persistent z pass (EL elements per lane) fits the 160 KB of LDS
+// a workgroup can hold: its pencil buffer plus the copy of the column twiddles.
+template <typename T, int P, int FAM, int EL, int MT> constexpr bool z_pf_fits()
+{
+    constexpr int B = PrunedShape<T>::ZB;
+    using TL = TileZConv<T, P, FAM, B, wave_threads(B, P, EL), true, MT>;
+    using RF = typename PlanFor<P, FAM>::Fwd;
+    using RI = typename PlanFor<P, FAM>::Inv;
+    constexpr int C = RF::tw_size() + (std::is_same<RF, RI>::value ? 0 : RI::tw_size());
+    return (TL::LDS + C) * (int)sizeof(cx<T>) <= 160 * 1024;
+}
+
 // Workgroups of `kernel` (nt threads) resident on the device at once, rounded
 // down to a multiple of 8 (the XCD count); a fallback if the query fails.
 template <class K> static int resident_workgroups(K kernel, int nt)
@@ -115,13 +127,14 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else (v.y_fam & 2) ? L0::y_fwd_pf(b) : L0::y_fwd(b);
             break;
         case 2:
-            if constexpr (MT == 0 && PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1) {
+            // (a persistent form that does not fit in LDS runs as the wave-owned pass)
+            if constexpr (MT == 0 && PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1 && z_pf_fits<T, P, F1 ? 1 : 0, 32, MT>()) {
                 if (v.zmode == 3) {  // persistent: radix-32 family where it exists
                     L1::template z_conv_pf<32>(b);
                     break;
                 }
             }
-            if constexpr (MT == 0 && PlanFor<P, 0>::Fwd::S > 1) {
+            if constexpr (MT == 0 && PlanFor<P, 0>::Fwd::S > 1 && z_pf_fits<T, P, 0, 16, MT>()) {
                 if (v.zmode == 4) {  // persistent: radix-16 family, one 1024-point pencil per wavefront
                     L0::template z_conv_pf<16>(b);
                     break;
@@ -153,8 +166,7 @@ template <typename T, int MT> static hipError_t pruned_dispatch(int P, int lo, i
     switch (P) {
 #define PS_CASE(PP) \
     case PP: return pruned_passes<T, PP, MT>(lo, hi, b);
-        PS_CASE(16) PS_CASE(32) PS_CASE(48) PS_CASE(64) PS_CASE(96) PS_CASE(128)
-        PS_CASE(192) PS_CASE(256) PS_CASE(384) PS_CASE(512) PS_CASE(768) PS_CASE(1024)
+        PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
     default: return hipErrorInvalidValue;
     }

@@ -1,6 +1,7 @@
 // Radix factorisations for the supported padded lengths P = 2N.
 //
-// Every supported P is 2^a or 3 * 2^a with 16 <= P <= 1024.  The forward plan
+// Every supported P is 16 m, P <= 1024, with m free of prime factors above 5
+// (P = 2^a 3^b 5^c, a >= 4).  The forward plan
 // starts with radix 16 (so zero padding of half the pencil removes half of
 // the first stage's inputs at compile time) and the inverse plan is the
 // forward plan reversed (so it ends with radix 16 and cropping removes half
@@ -25,6 +26,27 @@ template <> struct PlanFor<384, 0> { using Fwd = Radices<16, 3, 8>; using Inv = 
 template <> struct PlanFor<512, 0> { using Fwd = Radices<16, 2, 16>; using Inv = Radices<16, 2, 16>; };
 template <> struct PlanFor<768, 0> { using Fwd = Radices<16, 3, 16>; using Inv = Radices<16, 3, 16>; };
 template <> struct PlanFor<1024, 0> { using Fwd = Radices<16, 4, 16>; using Inv = Radices<16, 4, 16>; };
+// lengths with factors 3^2 or 5
+template <> struct PlanFor<80, 0> { using Fwd = Radices<16, 5>; using Inv = Radices<5, 16>; };
+template <> struct PlanFor<144, 0> { using Fwd = Radices<16, 3, 3>; using Inv = Radices<3, 3, 16>; };
+template <> struct PlanFor<160, 0> { using Fwd = Radices<16, 5, 2>; using Inv = Radices<2, 5, 16>; };
+template <> struct PlanFor<240, 0> { using Fwd = Radices<16, 3, 5>; using Inv = Radices<5, 3, 16>; };
+template <> struct PlanFor<288, 0> { using Fwd = Radices<16, 3, 3, 2>; using Inv = Radices<2, 3, 3, 16>; };
+template <> struct PlanFor<320, 0> { using Fwd = Radices<16, 5, 4>; using Inv = Radices<4, 5, 16>; };
+template <> struct PlanFor<400, 0> { using Fwd = Radices<16, 5, 5>; using Inv = Radices<5, 5, 16>; };
+template <> struct PlanFor<432, 0> { using Fwd = Radices<16, 3, 3, 3>; using Inv = Radices<3, 3, 3, 16>; };
+template <> struct PlanFor<480, 0> { using Fwd = Radices<16, 3, 5, 2>; using Inv = Radices<2, 5, 3, 16>; };
+template <> struct PlanFor<576, 0> { using Fwd = Radices<16, 3, 3, 4>; using Inv = Radices<4, 3, 3, 16>; };
+template <> struct PlanFor<640, 0> { using Fwd = Radices<16, 5, 8>; using Inv = Radices<8, 5, 16>; };
+template <> struct PlanFor<720, 0> { using Fwd = Radices<16, 3, 3, 5>; using Inv = Radices<5, 3, 3, 16>; };
+template <> struct PlanFor<800, 0> { using Fwd = Radices<16, 5, 5, 2>; using Inv = Radices<2, 5, 5, 16>; };
+template <> struct PlanFor<864, 0> { using Fwd = Radices<16, 3, 3, 3, 2>; using Inv = Radices<2, 3, 3, 3, 16>; };
+template <> struct PlanFor<960, 0> { using Fwd = Radices<16, 3, 5, 4>; using Inv = Radices<4, 5, 3, 16>; };
+
+// Every supported P, for the launchers' switch statements.
+#define PS_FOR_EACH_P(X)                                                                                      \
+    X(16) X(32) X(48) X(64) X(80) X(96) X(128) X(144) X(160) X(192) X(240) X(256) X(288) X(320) X(384)    \
+    X(400) X(432) X(480) X(512) X(576) X(640) X(720) X(768) X(800) X(864) X(960) X(1024)
 
 // Family 1: radix 32 first, one stage fewer (one LDS exchange fewer per
 // transform) where P allows it.

@@ -107,6 +107,31 @@ template <int DIR, typename V> __device__ __forceinline__ void dft3(V* v)
     v[2] = csub(m, s);
 }
 
+// 5 points: with t1 = a1 + a4, t2 = a2 + a3, t3 = a1 - a4, t4 = a2 - a3,
+// X1,4 = a0 + c1 t1 + c2 t2 +- DIR i (s1 t3 + s2 t4) and
+// X2,3 = a0 + c2 t1 + c1 t2 +- DIR i (s2 t3 - s1 t4), c_k = cos(2 pi k / 5),
+// s_k = sin(2 pi k / 5).
+template <int DIR, typename V> __device__ __forceinline__ void dft5(V* v)
+{
+    using T = decltype(v[0].x);
+    constexpr double C1 = 0.30901699437494742410;   // cos(2 pi / 5)
+    constexpr double C2 = -0.80901699437494742410;  // cos(4 pi / 5)
+    constexpr double S1 = 0.95105651629515357212;   // sin(2 pi / 5)
+    constexpr double S2 = 0.58778525229247312917;   // sin(4 pi / 5)
+    const T c1 = T(C1), c2 = T(C2), s1 = T(S1), s2 = T(S2);
+    const V a0 = v[0];
+    const V t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]), t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const V m1 = V{a0.x + c1 * t1.x + c2 * t2.x, a0.y + c1 * t1.y + c2 * t2.y};
+    const V m2 = V{a0.x + c2 * t1.x + c1 * t2.x, a0.y + c2 * t1.y + c1 * t2.y};
+    const V u1 = crot<DIR>(V{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
+    const V u2 = crot<DIR>(V{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
+    v[0] = V{a0.x + t1.x + t2.x, a0.y + t1.y + t2.y};
+    v[1] = cadd(m1, u1);
+    v[4] = csub(m1, u1);
+    v[2] = cadd(m2, u2);
+    v[3] = csub(m2, u2);
+}
+
 template <int DIR, typename V> __device__ __forceinline__ void dft8(V* v)
 {
     V e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
@@ -212,6 +237,7 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
     } else if constexpr (R == 2) dft2<DIR>(v);
     else if constexpr (R == 3) dft3<DIR>(v);
     else if constexpr (R == 4) dft4<DIR>(v);
+    else if constexpr (R == 5) dft5<DIR>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
     else if constexpr (R == 32) dft32<DIR>(v);

@@ -166,12 +166,15 @@ template <typename T> void append_table(std::vector<unsigned char>& blob, size_t
     }
 }
 
+// P = 2n = 16 m with 1 <= m <= 64 and no prime factor of m above 5 (the
+// lengths the radix plans cover).
 bool supported_n(int n)
 {
-    static const int ok[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
-    for (int v : ok)
-        if (v == n) return true;
-    return false;
+    if (n < 8 || n > 512 || n % 8 != 0) return false;
+    int m = n / 8;
+    for (int f : {2, 3, 5})
+        while (m % f == 0) m /= f;
+    return m == 1;
 }
 
 bool capturing(hipStream_t s, bool& cap, hipError_t& err)
@@ -408,7 +411,7 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     if (n <= 0) return fail(PS_ERR_INVALID, "n must be positive");
     if (!supported_n(n))
         return fail(PS_ERR_UNSUPPORTED, "n = " + std::to_string(n) +
-                                            " unsupported (2n must be 2^a or 3*2^a with 16 <= 2n <= 1024)");
+                                            " unsupported (2n must be 16 m <= 1024 with m having no prime factor above 5)");
     ps_plan p = new (std::nothrow) ps_plan_s();
     if (!p) return fail(PS_ERR_INVALID, "out of host memory");
     p->n = n;

@@ -35,7 +35,9 @@ PS_F32_PLAIN = 4
 PRECISIONS = {"f64": PS_F64, "f32": PS_F32, "f32_split": PS_F32_SPLIT,
               "f64_plain": PS_F64_PLAIN, "f32_plain": PS_F32_PLAIN}
 
-SUPPORTED_N = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
+# N = 8 m, m <= 64 with no prime factor above 5 (P = 2N = 2^a 3^b 5^c, a >= 4)
+SUPPORTED_N = (8, 16, 24, 32, 40, 48, 64, 72, 80, 96, 120, 128, 144, 160, 192, 200, 216, 240, 256, 288, 320, 360,
+               384, 400, 432, 480, 512)
 
 EXPORTS = ("ps_plan_create", "ps_plan_workspace_bytes", "ps_plan_query", "ps_green_build", "ps_solve",
            "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass",

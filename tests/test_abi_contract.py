@@ -47,7 +47,8 @@ def test_status_strings():
     (32, float("inf"), S.PS_F32, S.PS_ERR_INVALID),
     (32, 0.1, 7, S.PS_ERR_INVALID),
     (32, 0.1, -1, S.PS_ERR_INVALID),
-    (40, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),   # 80 = 2^4 * 5
+    (56, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),   # 112 = 2^4 * 7
+    (44, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),   # 88 = 2^3 * 11
     (1024, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),  # beyond the largest compiled length
     (7, 0.1, S.PS_F64, S.PS_ERR_UNSUPPORTED),
 ])
@@ -73,7 +74,7 @@ def test_plan_layout_and_query(n, prec):
         assert not info["ready"]
         prod = 1
         for r in info["radices"]:
-            assert r in (2, 3, 4, 8, 16)
+            assert r in (2, 3, 4, 5, 8, 16)
             prod *= r
         assert prod == 2 * n
         assert info["radices"][0] == 16

@@ -54,7 +54,7 @@ def _ghat_octant(n, dx, G=1.0):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
-@pytest.mark.parametrize("n", [8, 24, 32, 48])
+@pytest.mark.parametrize("n", [8, 24, 32, 40, 48, 72])
 def test_passes_match_numpy(prec, n):
     rng = np.random.default_rng(n)
     p, h = 2 * n, n + 1
@@ -122,6 +122,37 @@ def test_solve_matches_oracle_fft_conv(prec, n):
     ref = oracle.fft_conv(rho_used, 1.0 / n)
     l2, mx = _report(f"n={n} {prec}", got, ref)
     assert l2 <= TOL[prec]
+
+
+# lengths with factors 3^2 and 5 (radix-5 and repeated radix-3 stages)
+_SMOOTH_REF = {}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f64_plain", "f32_plain", "f32_split"])
+@pytest.mark.parametrize("n", [40, 72, 80, 120, 200])
+def test_five_smooth_sizes_match_oracle(prec, n):
+    rho = inputs.make_density(n, 8, 700 + n, sigma=(0.03, 0.1), noise=1e-3)
+    got, rho_used, s = gpu_solve(rho, prec)
+    assert 5 in s.info()["radices"] or n % 9 == 0
+    key = (n, prec.startswith("f64"))
+    if key not in _SMOOTH_REF:
+        _SMOOTH_REF[key] = oracle.fft_conv(rho_used, 1.0 / n)
+    l2, mx = _report(f"n={n} {prec}", got, _SMOOTH_REF[key])
+    assert l2 <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [216, 240, 320, 360, 400, 432, 480])
+def test_five_smooth_large_sampled_direct_sum(prec, n):
+    rho = inputs.make_density(n, 24, 800 + n, sigma=(0.01, 0.05), noise=1e-3)
+    got, rho_used, s = gpu_solve(rho, prec)
+    cells = _sample_cells(n, 16, n)
+    ref = oracle.direct_sum_cells(rho_used, cells, 1.0 / n)
+    g = got[cells[:, 0], cells[:, 1], cells[:, 2]]
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print(f"n={n} {prec} radices {s.info()['radices']} variants {s.info()['variant']}: sampled rel max err {err:.3e}",
+          flush=True)
+    assert err <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f64_plain", "f32_plain"])
@@ -296,7 +327,7 @@ def test_variants_agree_n256(prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("n", [16, 48, 96])
+@pytest.mark.parametrize("n", [16, 48, 96, 120])
 @pytest.mark.parametrize("zmode", [0, 1, 3, 4])
 def test_zmodes_match_oracle(prec, n, zmode):
     rho = inputs.make_density(n, 5, 500 + n, sigma=(0.03, 0.1), noise=1e-3)
