@@ -149,7 +149,10 @@ ps_status ps_solve_host(ps_plan p, const void *const *h_rho, void *const *h_phi,
  * synchronises `stream`, so it must not be under stream capture
  * (PS_ERR_CAPTURE); later calls with the same list upload nothing, do not
  * synchronise and can be captured into a HIP graph.  The same plan must not
- * lead two batches in flight at once. */
+ * lead two batches in flight at once.  A captured batch reads the records
+ * from plans[0]'s workspace each time the graph runs: once plans[0] has led
+ * a different list, call the captured list once more outside capture (which
+ * uploads its records again) before replaying that graph. */
 ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d_rho, void *const *d_phi,
                            void *stream);
 
