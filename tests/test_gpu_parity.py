@@ -340,6 +340,20 @@ def test_zmodes_match_oracle(prec, n, zmode):
     assert l2 <= TOL[prec]
 
 
+def test_persistent_z_fallback_where_lds_is_short():
+    # FP64 at P = 960: the persistent z pass does not fit in LDS, so variants
+    # 3 and 4 run the wave-owned pass (the same kernel as variant 1)
+    n = 480
+    rho = inputs.make_density(n, 6, 4800, sigma=(0.02, 0.06), noise=1e-3)
+    s = S.Solver(n, 1.0 / n, "f64")
+    r = torch.from_numpy(rho).to("cuda", torch.float64)
+    S.ps_plan_set_variant(s.plan, 2, 1)
+    ref = s(r)
+    for zmode in (3, 4):
+        S.ps_plan_set_variant(s.plan, 2, zmode)
+        assert torch.equal(s(r), ref), zmode
+
+
 def test_autotune_writes_cache(tmp_path):
     n = 64
     s = S.Solver(n, 1.0 / n, "f32")
