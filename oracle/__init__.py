@@ -13,8 +13,14 @@ ctypes.  Functions:
 * :func:`fft_conv`          -- the same via zero padding to 2N and full complex DFTs
 * :func:`fft_conv_kernel`   -- as ``fft_conv`` with a caller-supplied padded kernel
 * :func:`kernel_pad`, :func:`green_hat`, :func:`fft`, :func:`fft3`
+* :func:`direct_sum3`, :func:`direct_sum_cells3`, :func:`fft_conv3`,
+  :func:`kernel_pad3`, :func:`kernel_value3` -- the same on cells of spacings
+  dx, dy, dz (x, y, z); :func:`cell_average_inv_r` -- the self-cell average
+  of 1/|r| over such a cell
 
 Kernel: K(d) = -1/(dx |d|) for d != 0, K(0) = -self_coeff/dx (default 2.38).
+On dx x dy x dz cells: K(d) = -1/|(di dx, dj dy, dk dz)| and, unless the cell
+is a cube, K(0) = -(self_coeff / (3 ln(2 + sqrt 3) - pi/2)) * cell_average_inv_r.
 """
 from __future__ import annotations
 
@@ -60,6 +66,12 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "or_green_hat": ([i, d, d, dp], i),
         "or_fft_conv_kernel": ([i, d, d, dp, dp, dp], i),
         "or_fft_conv": ([i, d, d, d, dp, dp], i),
+        "or_cell_average_inv_r": ([d, d, d], d),
+        "or_kernel_value3": ([ctypes.c_long, ctypes.c_long, ctypes.c_long, d, d, d, d], d),
+        "or_direct_sum3": ([i, d, d, d, d, d, dp, dp], i),
+        "or_direct_sum_cells3": ([i, d, d, d, d, d, dp, i, ip, dp], i),
+        "or_kernel_pad3": ([i, d, d, d, d, dp], i),
+        "or_fft_conv3": ([i, d, d, d, d, d, dp, dp], i),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -170,6 +182,44 @@ class Oracle:
         _check(self.lib.or_fft_conv(rho.shape[0], dx, G, self_coeff, _dp(rho), _dp(phi)), "fft_conv")
         return phi
 
+    # cells of spacings dx, dy, dz along x, y, z
+    def cell_average_inv_r(self, dx: float, dy: float, dz: float) -> float:
+        return self.lib.or_cell_average_inv_r(float(dx), float(dy), float(dz))
+
+    def kernel_value3(self, di: int, dj: int, dk: int, dx: float, dy: float, dz: float,
+                      self_coeff: float = SELF_COEFF) -> float:
+        return self.lib.or_kernel_value3(int(di), int(dj), int(dk), float(dx), float(dy), float(dz), float(self_coeff))
+
+    def direct_sum3(self, rho: np.ndarray, dx: float, dy: float, dz: float, G: float = 1.0,
+                    self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = _cube(rho)
+        phi = np.empty_like(rho)
+        _check(self.lib.or_direct_sum3(rho.shape[0], dx, dy, dz, G, self_coeff, _dp(rho), _dp(phi)), "direct_sum3")
+        return phi
+
+    def direct_sum_cells3(self, rho: np.ndarray, cells: Sequence[Sequence[int]], dx: float, dy: float, dz: float,
+                          G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = _cube(rho)
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+        out = np.empty(c.shape[0], dtype=np.float64)
+        rc = self.lib.or_direct_sum_cells3(rho.shape[0], dx, dy, dz, G, self_coeff, _dp(rho), int(c.shape[0]),
+                                           c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out))
+        _check(rc, "direct_sum_cells3")
+        return out
+
+    def kernel_pad3(self, n: int, dx: float, dy: float, dz: float, self_coeff: float = SELF_COEFF) -> np.ndarray:
+        p = 2 * n
+        k = np.empty((p, p, p), dtype=np.float64)
+        _check(self.lib.or_kernel_pad3(n, dx, dy, dz, self_coeff, _dp(k)), "kernel_pad3")
+        return k
+
+    def fft_conv3(self, rho: np.ndarray, dx: float, dy: float, dz: float, G: float = 1.0,
+                  self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = _cube(rho)
+        phi = np.empty_like(rho)
+        _check(self.lib.or_fft_conv3(rho.shape[0], dx, dy, dz, G, self_coeff, _dp(rho), _dp(phi)), "fft_conv3")
+        return phi
+
     @staticmethod
     def rel_l2(a, ref):
         return rel_l2(a, ref)
@@ -204,6 +254,12 @@ kernel_pad = _default.kernel_pad
 green_hat = _default.green_hat
 fft_conv_kernel = _default.fft_conv_kernel
 fft_conv = _default.fft_conv
+cell_average_inv_r = _default.cell_average_inv_r
+kernel_value3 = _default.kernel_value3
+direct_sum3 = _default.direct_sum3
+direct_sum_cells3 = _default.direct_sum_cells3
+kernel_pad3 = _default.kernel_pad3
+fft_conv3 = _default.fft_conv3
 
 
 def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:

@@ -38,6 +38,14 @@
  * Sign convention: forward uses exp(-2 pi i jk / n), inverse exp(+2 pi i jk / n),
  * neither normalised.
  *
+ * Cells with spacings dx, dy, dz along x, y, z (the "3" routines): the
+ * displacement length is |(di dx, dj dy, dk dz)|, the volume factor dx dy dz,
+ * and the self cell takes the cell average of 1/|r| over the dx x dy x dz
+ * box (closed form below) scaled by self_coeff / (3 ln(2 + sqrt 3) - pi/2),
+ * the factor that turns the exact unit-cube average into self_coeff; a cube
+ * gets exactly -self_coeff/dx.  (The paper's cells are cubes; this reading
+ * extends its self-cell value to boxes.)
+ *
  * All arithmetic is IEEE double.  OpenMP parallelises over output cells and
  * over pencils only; each result is computed by one thread in a fixed order,
  * so results do not depend on the thread count.
@@ -338,11 +346,22 @@ int or_green_hat(int n, double dx, double self_coeff, double *ghat)
     return fft3_inplace(p, g, -1);
 }
 
+/* phi = gv Re(IDFT(DFT(rho_pad) * DFT(kpad)) / P^3)[0,N)^3, gv = G times the
+ * cell volume (each caller forms it). */
+static int conv_core(int n, double gv, const double *kpad, const double *rho, double *phi);
+
 /* Convolution theorem with a caller-supplied padded kernel kpad (P^3 real,
  * P = 2N): phi = G dx^3 Re(IDFT(DFT(rho_pad) * DFT(kpad)) / P^3)[0,N)^3. */
 int or_fft_conv_kernel(int n, double dx, double g, const double *kpad, const double *rho, double *phi)
 {
     if (n <= 0 || dx <= 0.0 || !kpad || !rho || !phi) return OR_ERR_ARG;
+    double gv = g * dx * dx * dx;
+    if (MUT(5)) gv = g * dx * dx;
+    return conv_core(n, gv, kpad, rho, phi);
+}
+
+static int conv_core(int n, double gv, const double *kpad, const double *rho, double *phi)
+{
     const int p = 2 * n;
     const long m = (long)p * p * p;
     cplx *a = (cplx *)calloc((size_t)m, sizeof(cplx));
@@ -365,9 +384,8 @@ int or_fft_conv_kernel(int n, double dx, double g, const double *kpad, const dou
         rc = fft3_inplace(p, a, +1);
     }
     if (!rc) {
-        double scale = g * dx * dx * dx / (double)m;
-        if (MUT(4)) scale = g * dx * dx * dx;
-        if (MUT(5)) scale = g * dx * dx / (double)m;
+        double scale = gv / (double)m;
+        if (MUT(4)) scale = gv;
 #pragma omp parallel for schedule(static)
         for (long z = 0; z < n; ++z)
             for (long y = 0; y < n; ++y)
@@ -389,6 +407,120 @@ int or_fft_conv(int n, double dx, double g, double self_coeff, const double *rho
     if (!k) return OR_ERR_NOMEM;
     int rc = or_kernel_pad(n, dx, self_coeff, k);
     if (!rc) rc = or_fft_conv_kernel(n, dx, g, k, rho, phi);
+    free(k);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Cells with spacings dx, dy, dz.
+ * ------------------------------------------------------------------------- */
+
+/* Integral of 1/|r| over the box [0,a] x [0,b] x [0,c], a, b, c > 0:
+ *   bc asinh(a / sqrt(b^2+c^2)) + ca asinh(b / sqrt(c^2+a^2)) + ab asinh(c / sqrt(a^2+b^2))
+ *   - a^2/2 atan(bc / (a r)) - b^2/2 atan(ca / (b r)) - c^2/2 atan(ab / (c r)),
+ * r = sqrt(a^2 + b^2 + c^2) (integrate 1/r along one axis, then the other two). */
+static double inv_r_box(double a, double b, double c)
+{
+    const double r = sqrt(a * a + b * b + c * c);
+    return b * c * asinh(a / hypot(b, c)) + c * a * asinh(b / hypot(c, a)) + a * b * asinh(c / hypot(a, b)) -
+           0.5 * a * a * atan(b * c / (a * r)) - 0.5 * b * b * atan(c * a / (b * r)) -
+           0.5 * c * c * atan(a * b / (c * r));
+}
+
+/* Average of 1/|r| over a dx x dy x dz cell centred on the origin (eight octants). */
+double or_cell_average_inv_r(double dx, double dy, double dz)
+{
+    if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0)) return NAN;
+    return 8.0 * inv_r_box(0.5 * dx, 0.5 * dy, 0.5 * dz) / (dx * dy * dz);
+}
+
+/* K(d) for an integer displacement (di, dj, dk) on cells dx x dy x dz. */
+double or_kernel_value3(long di, long dj, long dk, double dx, double dy, double dz, double self_coeff)
+{
+    if (di == 0 && dj == 0 && dk == 0) {
+        if ((dx == dy && dy == dz) || MUT(11)) return -self_coeff / dx;
+        const double unit_cube = 3.0 * log(2.0 + sqrt(3.0)) - 2.0 * atan(1.0);  /* 3 ln(2 + sqrt 3) - pi/2 */
+        return -(self_coeff / unit_cube) * or_cell_average_inv_r(dx, dy, dz);
+    }
+    const double x = (double)di * dx, y = (double)dj * (MUT(12) ? dz : dy), z = (double)dk * (MUT(12) ? dy : dz);
+    return -1.0 / sqrt(x * x + y * y + z * z);
+}
+
+static double *kernel_table3(int n, double dx, double dy, double dz, double self_coeff)
+{
+    size_t m = (size_t)n * n * n;
+    double *k = (double *)malloc(m * sizeof(double));
+    if (!k) return NULL;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            for (int c = 0; c < n; ++c)
+                k[((size_t)a * n + b) * n + c] = or_kernel_value3(c, b, a, dx, dy, dz, self_coeff);
+    return k;
+}
+
+static int bad_spacing(double dx, double dy, double dz) { return !(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0); }
+
+/* phi = G dx dy dz sum_j K(i-j) rho[j] on all N^3 cells. */
+int or_direct_sum3(int n, double dx, double dy, double dz, double g, double self_coeff, const double *rho,
+                   double *phi)
+{
+    if (n <= 0 || bad_spacing(dx, dy, dz) || !rho || !phi) return OR_ERR_ARG;
+    double *ktab = kernel_table3(n, dx, dy, dz, self_coeff);
+    if (!ktab) return OR_ERR_NOMEM;
+    const double scale = g * dx * dy * dz;
+    const long m = (long)n * n * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long c = 0; c < m; ++c) {
+        int iz = (int)(c / ((long)n * n)), iy = (int)((c / n) % n), ix = (int)(c % n);
+        phi[c] = scale * direct_one(n, ktab, rho, iz, iy, ix);
+    }
+    free(ktab);
+    return OR_OK;
+}
+
+int or_direct_sum_cells3(int n, double dx, double dy, double dz, double g, double self_coeff, const double *rho,
+                         int ncells, const int *cells, double *out)
+{
+    if (n <= 0 || bad_spacing(dx, dy, dz) || !rho || !out || ncells < 0 || (ncells > 0 && !cells)) return OR_ERR_ARG;
+    for (int c = 0; c < ncells; ++c)
+        for (int a = 0; a < 3; ++a)
+            if (cells[3 * c + a] < 0 || cells[3 * c + a] >= n) return OR_ERR_ARG;
+    double *ktab = kernel_table3(n, dx, dy, dz, self_coeff);
+    if (!ktab) return OR_ERR_NOMEM;
+    const double scale = g * dx * dy * dz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < ncells; ++c)
+        out[c] = scale * direct_one(n, ktab, rho, cells[3 * c], cells[3 * c + 1], cells[3 * c + 2]);
+    free(ktab);
+    return OR_OK;
+}
+
+/* kpad[z][y][x] = K(min(x,P-x), min(y,P-y), min(z,P-z)) on dx x dy x dz cells. */
+int or_kernel_pad3(int n, double dx, double dy, double dz, double self_coeff, double *kpad)
+{
+    if (n <= 0 || bad_spacing(dx, dy, dz) || !kpad) return OR_ERR_ARG;
+    const int p = 2 * n;
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < p; ++z)
+        for (long y = 0; y < p; ++y)
+            for (long x = 0; x < p; ++x) {
+                const long az = z < p - z ? z : p - z, ay = y < p - y ? y : p - y, ax = x < p - x ? x : p - x;
+                kpad[(z * p + y) * p + x] = or_kernel_value3(ax, ay, az, dx, dy, dz, self_coeff);
+            }
+    return OR_OK;
+}
+
+/* The FFT-convolution solve on dx x dy x dz cells. */
+int or_fft_conv3(int n, double dx, double dy, double dz, double g, double self_coeff, const double *rho,
+                 double *phi)
+{
+    if (n <= 0 || bad_spacing(dx, dy, dz) || !rho || !phi) return OR_ERR_ARG;
+    const int p = 2 * n;
+    const long m = (long)p * p * p;
+    double *k = (double *)malloc((size_t)m * sizeof(double));
+    if (!k) return OR_ERR_NOMEM;
+    int rc = or_kernel_pad3(n, dx, dy, dz, self_coeff, k);
+    if (!rc) rc = conv_core(n, MUT(13) ? g * dx * dx * dx : g * dx * dy * dz, k, rho, phi);
     free(k);
     return rc;
 }

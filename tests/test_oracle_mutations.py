@@ -23,6 +23,9 @@ MUTATIONS = {
     8: "crop shifted by one cell in x",
     9: "combine twiddle exponent uses k instead of k + s m",
     10: "1/r^2 kernel instead of 1/r",
+    11: "box self cell ignores the spacings",
+    12: "y and z spacings swapped in the kernel on dx x dy x dz cells",
+    13: "dx^3 instead of dx dy dz as the cell volume",
 }
 
 CHECKS = [
@@ -34,6 +37,9 @@ CHECKS = [
     lambda o: pins.test_impulse_response_is_the_kernel(o, 12, (0, 11, 6)),
     lambda o: pins.test_green_hat_real_and_even(o, 6),
     lambda o: pins.test_gaussian_sphere_closed_form_second_order(o),
+    lambda o: pins.test_box_self_cell_scales_like_the_cube(o),
+    lambda o: pins.test_anisotropic_impulse_response_and_axis_swap(o),
+    lambda o: pins.test_anisotropic_monopole_far_field(o),
 ]
 
 

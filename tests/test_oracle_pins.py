@@ -251,3 +251,84 @@ def test_monopole_far_field(oracle_lib):
     m = rho.sum() * dx ** 3
     for idx in [(0, 0, 0), (0, 0, n - 1), (n - 1, n - 1, n - 1), (0, n - 1, 0)]:
         assert abs(phi[idx] - (-m / r[idx])) <= 1e-4 * abs(m / r[idx])
+
+
+# --------------------------------------------------------------------------
+# Cells of spacings dx, dy, dz (the "3" routines).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("box", [(1.0, 1.0, 1.0), (1.0, 2.0, 3.0), (1.0, 1.0, 4.0), (0.5, 1.0, 1.0)])
+def test_cell_average_of_inv_r_by_quadrature(oracle_lib, box):
+    # the closed form against adaptive cubature of 1/|r| over one octant
+    from scipy import integrate
+    a, b, c = (0.5 * v for v in box)
+    val, _ = integrate.tplquad(lambda z, y, x: 1.0 / math.sqrt(x * x + y * y + z * z), 0, a, 0, b, 0, c,
+                               epsabs=1e-12, epsrel=1e-11)
+    want = 8.0 * val / (box[0] * box[1] * box[2])
+    assert abs(oracle_lib.cell_average_inv_r(*box) - want) <= 1e-9 * want
+    if box == (1.0, 1.0, 1.0):  # the self-cell constant of the cube, 3 ln(2 + sqrt 3) - pi/2
+        assert abs(oracle_lib.cell_average_inv_r(*box) - (3 * math.log(2 + math.sqrt(3)) - math.pi / 2)) < 1e-15
+
+
+def test_box_self_cell_scales_like_the_cube(oracle_lib):
+    # a cube gives exactly the cubic kernel's -self_coeff/dx; a box gives the
+    # cell average scaled by self_coeff over the unit-cube average; K is
+    # homogeneous of degree -1 in the spacings
+    assert oracle_lib.kernel_value3(0, 0, 0, 0.1, 0.1, 0.1) == oracle_lib.kernel_value(0, 0, 0, 0.1)
+    unit = 3 * math.log(2 + math.sqrt(3)) - math.pi / 2
+    k0 = oracle_lib.kernel_value3(0, 0, 0, 0.1, 0.2, 0.3, self_coeff=2.38)
+    assert abs(k0 + 2.38 / unit * oracle_lib.cell_average_inv_r(0.1, 0.2, 0.3)) < 1e-14 * abs(k0)
+    assert abs(oracle_lib.kernel_value3(0, 0, 0, 0.2, 0.4, 0.6) - k0 / 2) < 1e-14 * abs(k0)
+    assert abs(oracle_lib.kernel_value3(2, -1, 3, 0.1, 0.2, 0.3) + 1 / math.sqrt(0.04 + 0.04 + 0.81)) < 1e-15
+
+
+def test_anisotropic_equals_cubic_for_equal_spacings(oracle_lib):
+    n = 12
+    rho = inputs.make_density(n, 3, 61, sigma=(0.05, 0.1))
+    a = oracle_lib.fft_conv3(rho, 1 / n, 1 / n, 1 / n)
+    b = oracle_lib.fft_conv(rho, 1 / n)
+    assert oracle_lib.rel_l2(a, b) < 1e-15
+
+
+@pytest.mark.parametrize("n,sp", [(8, (0.1, 0.2, 0.3)), (12, (0.3, 0.1, 0.17)), (16, (1 / 16, 1 / 8, 1 / 32))])
+def test_anisotropic_fft_conv_equals_direct_sum(oracle_lib, n, sp):
+    rho = inputs.make_density(n, 3, 70 + n, sigma=(0.05, 0.1), noise=1e-3)
+    a = oracle_lib.fft_conv3(rho, *sp, G=1.3)
+    b = oracle_lib.direct_sum3(rho, *sp, G=1.3)
+    assert oracle_lib.rel_l2(a, b) < 1e-13
+    cells = [[0, 0, 0], [n - 1, 2, 5], [3, n - 1, 1]]
+    c = oracle_lib.direct_sum_cells3(rho, cells, *sp, G=1.3)
+    assert np.allclose(c, [b[z, y, x] for z, y, x in cells], rtol=1e-15, atol=0)
+
+
+def test_anisotropic_impulse_response_and_axis_swap(oracle_lib):
+    # a unit mass in one cell: phi = G K(i - c) exactly; swapping the x and z
+    # axes of the density together with dx and dz transposes the potential
+    n, (dx, dy, dz) = 10, (0.1, 0.25, 0.4)
+    c = (2, 7, 4)  # (z, y, x)
+    rho = np.zeros((n, n, n))
+    rho[c] = 1.0 / (dx * dy * dz)
+    phi = oracle_lib.fft_conv3(rho, dx, dy, dz)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ref = np.vectorize(lambda a, b, cc: oracle_lib.kernel_value3(cc - c[2], b - c[1], a - c[0], dx, dy, dz))(z, y, x)
+    assert np.abs(phi - ref).max() <= 1e-14 * np.abs(ref).max()
+    rho2 = inputs.make_density(n, 3, 81, sigma=(0.05, 0.1))
+    a = oracle_lib.fft_conv3(rho2, dx, dy, dz)
+    b = oracle_lib.fft_conv3(np.ascontiguousarray(np.transpose(rho2, (2, 1, 0))), dz, dy, dx)
+    assert oracle_lib.rel_l2(np.transpose(b, (2, 1, 0)), a) < 1e-14
+
+
+def test_anisotropic_monopole_far_field(oracle_lib):
+    # a compact blob on stretched cells: far from it phi -> -G M / r with r
+    # measured in the cells' physical lengths
+    n, (dx, dy, dz) = 24, (1 / 24, 1 / 12, 1 / 48)
+    zc, yc, xc = (np.arange(n) + 0.5) * dz, (np.arange(n) + 0.5) * dy, (np.arange(n) + 0.5) * dx
+    z, y, x = np.meshgrid(zc, yc, xc, indexing="ij")
+    cz, cy, cx = zc[n // 2], yc[n // 2], xc[n // 2]
+    s = 0.02
+    rho = np.exp(-((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) / (2 * s * s))
+    mass = rho.sum() * dx * dy * dz
+    phi = oracle_lib.fft_conv3(rho, dx, dy, dz)
+    for (a, b, c) in [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1)]:
+        r = math.sqrt((z[a, b, c] - cz) ** 2 + (y[a, b, c] - cy) ** 2 + (x[a, b, c] - cx) ** 2)
+        assert abs(phi[a, b, c] + mass / r) <= 2e-3 * mass / r
