@@ -82,6 +82,7 @@ typedef struct {
     size_t t3_offset;       /* byte offset in the workspace of T3 (pruned plans; 0 otherwise) */
     int variant[5];         /* kernel variant of each pruned pass (see ps_plan_set_variant) */
     int split_terms;        /* PS_F32_SPLIT: split-bf16 product terms per DFT-16 (6 or 3); else 0 */
+    double dy, dz;          /* cell spacings along y and z (dx unless set by ps_plan_set_spacing) */
 } ps_plan_info;
 
 /* Create a plan for an n^3 grid of spacing dx (> 0) in the given precision.
@@ -174,6 +175,19 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * operand, all piece products of order <= 2; the default) or 3 (two pieces,
  * order <= 1). */
 ps_status ps_plan_set_variant(ps_plan p, int pass, int variant);
+
+/* Cells of spacings dx (the plan's), dy, dz along x, y, z instead of cubes
+ * (host only, no HIP call; the plan must be built again with
+ * ps_green_build before its next solve, else PS_ERR_NOT_READY).  The solve
+ * becomes phi[i] = G dx dy dz sum_j K(i - j) rho[j] with
+ * K(d) = -1 / |(d_x dx, d_y dy, d_z dz)| for d != 0 and, for a cell that is
+ * not a cube, K(0) = -(self_coeff / C) * A, where A is the average of 1/|r|
+ * over the dx x dy x dz cell centred on its centre (closed form) and
+ * C = 3 ln(2 + sqrt 3) - pi/2 = 2.38008 is that average over a unit cube
+ * (the paper's cells are cubes; this extends its self-cell value to boxes so
+ * that a cube gives K(0) = -self_coeff/dx exactly).  dy, dz must be positive
+ * and finite (PS_ERR_INVALID). */
+ps_status ps_plan_set_spacing(ps_plan p, double dy, double dz);
 
 /* Time every variant of every pass of a built pruned plan on its own
  * workspace (contents are overwritten), keep the fastest per pass and, if

@@ -2,7 +2,9 @@
 // per plan in double precision on the GPU.
 //
 // The padded kernel K_pad[z][y][x] = K(min(x,P-x), min(y,P-y), min(z,P-z)),
-// with K(d) = -1/(dx |d|) and K(0) = -self_coeff/dx, is real and even along
+// with K(d) = -1/(dx |(dx sx, dy sy, dz sz)|) for cells of spacings dx,
+// dx sy, dx sz (sx = 1; all ratios 1 for cubes) and K(0) = the self value
+// (-self_coeff/dx for cubes), is real and even along
 // every axis, so its 3D DFT is real and even and one octant [0,H)^3 holds all
 // of it.  Evenness also means that only the H x H rows with y, z in [0, H)
 // need a transform along x, and so on per axis.  Three passes:
@@ -11,7 +13,7 @@
 //            forward FFT along x, kx in [0,H) kept   -> G1[kx][z][y]
 //   green_y  pencils along y, even extension y -> min(y, P-y), in place
 //                                                    -> G1[kx][z][ky]
-//   green_z  pencils along z, even extension, scaled by G dx^3 / P^3 and
+//   green_z  pencils along z, even extension, scaled by G dV / P^3 and
 //            rounded once to the plan's type        -> Ghat[kx][ky][kz]
 //            (or Ghat[kz][ky][kx] for the plain method's layout)
 //
@@ -25,7 +27,7 @@ namespace ps {
 
 template <int P, int NT, int MAP_MID>
 __global__ __launch_bounds__(NT) void k_green_x(double* __restrict__ g1, const double2* __restrict__ tw,
-                                                double dx, double self_coeff)
+                                                double dx, double sy, double sz, double self_value)
 {
     using V = double2;
     using E = Engine<double, typename PlanFor<P>::Fwd, 8, NT>;
@@ -36,8 +38,9 @@ __global__ __launch_bounds__(NT) void k_green_x(double* __restrict__ g1, const d
     auto kv = [&](int x, int y) -> double {
         if (y >= H) return 0.0;
         const int ax = x <= N ? x : P - x;
-        const double r2 = double(ax) * ax + double(y) * y + double(z) * z;
-        return r2 == 0.0 ? -self_coeff / dx : -1.0 / (dx * sqrt(r2));
+        const double ry = double(y) * sy, rz = double(z) * sz;
+        const double r2 = double(ax) * ax + ry * ry + rz * rz;
+        return r2 == 0.0 ? self_value : -1.0 / (dx * sqrt(r2));
     };
     auto ld = [&](int p, int idx) -> V {
         const int ya = y0 + 2 * p;

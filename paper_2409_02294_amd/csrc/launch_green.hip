@@ -12,7 +12,8 @@ template <int P> static hipError_t green_passes(const GreenBufs& b)
     constexpr int NT = threads_for(8, P);
     const double2* tw = static_cast<const double2*>(b.twf64);
     const dim3 grid((H + 15) / 16, H);
-    hipLaunchKernelGGL((k_green_x<P, NT, MAP_EF>), grid, dim3(NT), 0, b.stream, b.g1, tw, b.dx, b.self_coeff);
+    hipLaunchKernelGGL((k_green_x<P, NT, MAP_EF>), grid, dim3(NT), 0, b.stream, b.g1, tw, b.dx, b.sy, b.sz,
+                       b.self_value);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_green_y<P, NT, MAP_EF>), grid, dim3(NT), 0, b.stream, b.g1, tw);

@@ -177,6 +177,26 @@ bool supported_n(int n)
     return m == 1;
 }
 
+// K(0) for cells of spacings dx, dy, dz: -self_coeff/dx for a cube; for a
+// box, the box's average of 1/|r| scaled by self_coeff over the unit cube's
+// average 3 ln(2 + sqrt 3) - pi/2 (so that the two agree on cubes).  The
+// average over the box [-a,a] x [-b,b] x [-c,c] is 8 F(a, b, c) / (8abc)
+// with F the integral of 1/|r| over [0,a] x [0,b] x [0,c]:
+//   F = bc asinh(a/sqrt(b^2+c^2)) + ca asinh(b/sqrt(c^2+a^2)) + ab asinh(c/sqrt(a^2+b^2))
+//       - (a^2 atan(bc/(a r)) + b^2 atan(ca/(b r)) + c^2 atan(ab/(c r))) / 2,  r = |(a, b, c)|.
+double self_value(double dx, double dy, double dz, double self_coeff)
+{
+    if (dx == dy && dy == dz) return -self_coeff / dx;
+    const double a = 0.5 * dx, b = 0.5 * dy, c = 0.5 * dz, r = std::sqrt(a * a + b * b + c * c);
+    const double f = b * c * std::asinh(a / std::hypot(b, c)) + c * a * std::asinh(b / std::hypot(c, a)) +
+                     a * b * std::asinh(c / std::hypot(a, b)) -
+                     0.5 * (a * a * std::atan(b * c / (a * r)) + b * b * std::atan(c * a / (b * r)) +
+                            c * c * std::atan(a * b / (c * r)));
+    const double average = f / (a * b * c);
+    const double unit_cube = 3.0 * std::log(2.0 + std::sqrt(3.0)) - 2.0 * std::atan(1.0);
+    return -self_coeff / unit_cube * average;
+}
+
 bool capturing(hipStream_t s, bool& cap, hipError_t& err)
 {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -195,7 +215,7 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb)
 
 struct ps_plan_s {
     int n = 0, P = 0, H = 0;
-    double dx = 0.0;
+    double dx = 0.0, dy = 0.0, dz = 0.0;  // cell spacings along x, y, z
     ps_precision prec = PS_F64;
     size_t real_bytes = 0;
     std::vector<int> radices;
@@ -418,6 +438,8 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     p->P = 2 * n;
     p->H = n + 1;
     p->dx = dx;
+    p->dy = dx;
+    p->dz = dx;
     p->prec = prec;
     p->real_bytes = is_f64(prec) ? 8 : 4;
     if (!ps::host_radices(p->P, p->radices)) {
@@ -523,6 +545,8 @@ ps_status ps_plan_query(ps_plan p, ps_plan_info* info)
     info->h = p->H;
     info->precision = (int)p->prec;
     info->dx = p->dx;
+    info->dy = p->dy;
+    info->dz = p->dz;
     info->workspace_bytes = p->ws_bytes;
     info->ghat_bytes = p->ghat_bytes;
     info->ready = p->ready ? 1 : 0;
@@ -559,9 +583,11 @@ ps_status ps_green_build(ps_plan p, void* d_workspace, double G, double self_coe
     gb.ghat = ws + p->off_ghat;
     gb.twf64 = ws + p->off_tab + p->tw_f64;
     gb.dx = p->dx;
-    gb.self_coeff = self_coeff;
+    gb.sy = p->dy / p->dx;
+    gb.sz = p->dz / p->dx;
+    gb.self_value = self_value(p->dx, p->dy, p->dz, self_coeff);
     const double P3 = (double)p->P * p->P * p->P;
-    gb.scale = G * p->dx * p->dx * p->dx / P3;
+    gb.scale = G * p->dx * p->dy * p->dz / P3;
     gb.out_f32 = !is_f64(p->prec);
     gb.plain_layout = is_plain(p->prec);
     gb.stream = st;
@@ -700,6 +726,18 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
     if (pass == 2 && variant >= 3 && p->prec == PS_F32_SPLIT)
         return fail(PS_ERR_UNSUPPORTED, "split plans have no persistent z pass");
     *variant_slot(p->var, pass) = variant;
+    return PS_OK;
+}
+
+ps_status ps_plan_set_spacing(ps_plan p, double dy, double dz)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (!(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dy) || !std::isfinite(dz))
+        return fail(PS_ERR_INVALID, "dy and dz must be positive and finite");
+    p->dy = dy;
+    p->dz = dz;
+    p->ready = false;  // the kernel spectrum depends on the spacings
+    p->batch_sig.clear();
     return PS_OK;
 }
 

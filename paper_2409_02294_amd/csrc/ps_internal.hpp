@@ -53,7 +53,10 @@ struct GreenBufs {
     double* g1;          // [H][H][H] scratch
     void* ghat;          // output, float or double
     const void* twf64;   // forward-plan twiddles in double
-    double dx, self_coeff, scale;
+    double dx;           // x spacing
+    double sy, sz;       // y and z spacings over dx (1 for cubic cells)
+    double self_value;   // K(0)
+    double scale;        // G dV / P^3
     bool out_f32;
     bool plain_layout;   // [kz][ky][kx] instead of [kx][ky][kz]
     hipStream_t stream;

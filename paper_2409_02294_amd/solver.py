@@ -41,7 +41,7 @@ SUPPORTED_N = (8, 16, 24, 32, 40, 48, 64, 72, 80, 96, 120, 128, 144, 160, 192, 2
 
 EXPORTS = ("ps_plan_create", "ps_plan_workspace_bytes", "ps_plan_query", "ps_green_build", "ps_solve",
            "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass",
-           "ps_plan_set_variant", "ps_autotune", "ps_host_stage_bytes", "ps_solve_host")
+           "ps_plan_set_variant", "ps_autotune", "ps_host_stage_bytes", "ps_solve_host", "ps_plan_set_spacing")
 
 
 class PSError(RuntimeError):
@@ -56,7 +56,7 @@ class PlanInfo(ctypes.Structure):
                 ("ready", ctypes.c_int), ("radices", ctypes.c_int * 8),
                 ("t1_offset", ctypes.c_size_t), ("t2_offset", ctypes.c_size_t), ("t3_offset", ctypes.c_size_t),
                 ("variant", ctypes.c_int * 5),
-                ("split_terms", ctypes.c_int)]
+                ("split_terms", ctypes.c_int), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -89,6 +89,7 @@ def load() -> ctypes.CDLL:
         "ps_last_error": ([], ctypes.c_char_p),
         "ps_debug_pass": ([vp, i, vp, vp, vp], i),
         "ps_plan_set_variant": ([vp, i, i], i),
+        "ps_plan_set_spacing": ([vp, ctypes.c_double, ctypes.c_double], i),
         "ps_autotune": ([vp, vp, ctypes.c_char_p], i),
     }
     for name, (args, res) in sig.items():
@@ -132,7 +133,8 @@ def ps_plan_query(plan: int) -> Dict:
     rad = [r for r in info.radices if r]
     return dict(n=info.n, p=info.p, h=info.h, precision=info.precision, dx=info.dx,
                 workspace_bytes=info.workspace_bytes, ghat_bytes=info.ghat_bytes, ready=bool(info.ready),
-                radices=rad, t1_offset=info.t1_offset, t2_offset=info.t2_offset, t3_offset=info.t3_offset, variant=list(info.variant), split_terms=info.split_terms)
+                radices=rad, t1_offset=info.t1_offset, t2_offset=info.t2_offset, t3_offset=info.t3_offset, variant=list(info.variant), split_terms=info.split_terms,
+                dy=info.dy, dz=info.dz)
 
 
 def ps_green_build(plan: int, workspace: int, G: float, self_coeff: float, stream: int) -> None:
@@ -179,6 +181,10 @@ def ps_plan_set_variant(plan: int, pass_id: int, variant: int) -> None:
     _check(load().ps_plan_set_variant(plan, int(pass_id), int(variant)), "ps_plan_set_variant")
 
 
+def ps_plan_set_spacing(plan: int, dy: float, dz: float) -> None:
+    _check(load().ps_plan_set_spacing(plan, float(dy), float(dz)), "ps_plan_set_spacing")
+
+
 def ps_autotune(plan: int, stream: int, cache_path: Optional[str] = None) -> None:
     cp = cache_path.encode() if cache_path else None
     _check(load().ps_autotune(plan, stream, cp), "ps_autotune")
@@ -197,7 +203,8 @@ class Solver:
     """
 
     def __init__(self, n: int, dx: Optional[float] = None, precision="f32", G: float = 1.0,
-                 self_coeff: float = 2.38, device=None, tune_cache: Optional[str] = None):
+                 self_coeff: float = 2.38, device=None, tune_cache: Optional[str] = None,
+                 spacing: Optional[tuple] = None):
         import torch
         self.torch = torch
         self.n = int(n)
@@ -206,6 +213,8 @@ class Solver:
         self.dtype = torch.float64 if self.precision in (PS_F64, PS_F64_PLAIN) else torch.float32
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.plan = ps_plan_create(self.n, self.dx, self.precision, tune_cache)
+        if spacing is not None:  # (dy, dz): cells of spacings dx, dy, dz
+            ps_plan_set_spacing(self.plan, spacing[0], spacing[1])
         nbytes = ps_plan_workspace_bytes(self.plan)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

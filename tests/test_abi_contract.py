@@ -165,6 +165,22 @@ def test_variant_selection_contract():
         S.ps_plan_destroy(q)
 
 
+def test_spacing_contract():
+    lib = S.load()
+    p = S.ps_plan_create(32, 0.1, S.PS_F64)
+    try:
+        info = S.ps_plan_query(p)
+        assert info["dx"] == 0.1 and info["dy"] == 0.1 and info["dz"] == 0.1
+        for dy, dz in [(0.0, 0.1), (0.1, -1.0), (float("nan"), 0.1), (0.1, float("inf"))]:
+            assert lib.ps_plan_set_spacing(p, dy, dz) == S.PS_ERR_INVALID
+        S.ps_plan_set_spacing(p, 0.2, 0.05)
+        info = S.ps_plan_query(p)
+        assert (info["dx"], info["dy"], info["dz"]) == (0.1, 0.2, 0.05) and not info["ready"]
+        assert lib.ps_plan_set_spacing(None, 0.1, 0.1) == S.PS_ERR_INVALID
+    finally:
+        S.ps_plan_destroy(p)
+
+
 def test_tuning_cache_is_read(tmp_path):
     path = tmp_path / "tune.txt"
     path.write_text("64 f32 0 0 0 0 0\n512 f32 0 1 1 0 1\n512 f64 1 1 2 1 1\n")
