@@ -26,22 +26,24 @@ template <> struct PlanFor<384, 0> { using Fwd = Radices<16, 3, 8>; using Inv = 
 template <> struct PlanFor<512, 0> { using Fwd = Radices<16, 2, 16>; using Inv = Radices<16, 2, 16>; };
 template <> struct PlanFor<768, 0> { using Fwd = Radices<16, 3, 16>; using Inv = Radices<16, 3, 16>; };
 template <> struct PlanFor<1024, 0> { using Fwd = Radices<16, 4, 16>; using Inv = Radices<16, 4, 16>; };
-// lengths with factors 3^2 or 5
+// lengths with factors 3^2 or 5; radices 6, 10, 12, 15, 20 are prime-factor
+// DFTs in registers (no inner twiddles), which saves a stage and its LDS
+// exchange against splitting them into their factors
 template <> struct PlanFor<80, 0> { using Fwd = Radices<16, 5>; using Inv = Radices<5, 16>; };
 template <> struct PlanFor<144, 0> { using Fwd = Radices<16, 3, 3>; using Inv = Radices<3, 3, 16>; };
-template <> struct PlanFor<160, 0> { using Fwd = Radices<16, 5, 2>; using Inv = Radices<2, 5, 16>; };
-template <> struct PlanFor<240, 0> { using Fwd = Radices<16, 3, 5>; using Inv = Radices<5, 3, 16>; };
-template <> struct PlanFor<288, 0> { using Fwd = Radices<16, 3, 3, 2>; using Inv = Radices<2, 3, 3, 16>; };
-template <> struct PlanFor<320, 0> { using Fwd = Radices<16, 5, 4>; using Inv = Radices<4, 5, 16>; };
+template <> struct PlanFor<160, 0> { using Fwd = Radices<16, 10>; using Inv = Radices<10, 16>; };
+template <> struct PlanFor<240, 0> { using Fwd = Radices<16, 15>; using Inv = Radices<15, 16>; };
+template <> struct PlanFor<288, 0> { using Fwd = Radices<16, 6, 3>; using Inv = Radices<3, 6, 16>; };
+template <> struct PlanFor<320, 0> { using Fwd = Radices<16, 20>; using Inv = Radices<20, 16>; };
 template <> struct PlanFor<400, 0> { using Fwd = Radices<16, 5, 5>; using Inv = Radices<5, 5, 16>; };
 template <> struct PlanFor<432, 0> { using Fwd = Radices<16, 3, 3, 3>; using Inv = Radices<3, 3, 3, 16>; };
-template <> struct PlanFor<480, 0> { using Fwd = Radices<16, 3, 5, 2>; using Inv = Radices<2, 5, 3, 16>; };
-template <> struct PlanFor<576, 0> { using Fwd = Radices<16, 3, 3, 4>; using Inv = Radices<4, 3, 3, 16>; };
+template <> struct PlanFor<480, 0> { using Fwd = Radices<16, 15, 2>; using Inv = Radices<2, 15, 16>; };
+template <> struct PlanFor<576, 0> { using Fwd = Radices<16, 12, 3>; using Inv = Radices<3, 12, 16>; };
 template <> struct PlanFor<640, 0> { using Fwd = Radices<16, 5, 8>; using Inv = Radices<8, 5, 16>; };
-template <> struct PlanFor<720, 0> { using Fwd = Radices<16, 3, 3, 5>; using Inv = Radices<5, 3, 3, 16>; };
-template <> struct PlanFor<800, 0> { using Fwd = Radices<16, 5, 5, 2>; using Inv = Radices<2, 5, 5, 16>; };
-template <> struct PlanFor<864, 0> { using Fwd = Radices<16, 3, 3, 3, 2>; using Inv = Radices<2, 3, 3, 3, 16>; };
-template <> struct PlanFor<960, 0> { using Fwd = Radices<16, 3, 5, 4>; using Inv = Radices<4, 5, 3, 16>; };
+template <> struct PlanFor<720, 0> { using Fwd = Radices<16, 15, 3>; using Inv = Radices<3, 15, 16>; };
+template <> struct PlanFor<800, 0> { using Fwd = Radices<16, 10, 5>; using Inv = Radices<5, 10, 16>; };
+template <> struct PlanFor<864, 0> { using Fwd = Radices<16, 6, 3, 3>; using Inv = Radices<3, 3, 6, 16>; };
+template <> struct PlanFor<960, 0> { using Fwd = Radices<16, 15, 4>; using Inv = Radices<4, 15, 16>; };
 
 // Every supported P, for the launchers' switch statements.
 #define PS_FOR_EACH_P(X)                                                                                      \

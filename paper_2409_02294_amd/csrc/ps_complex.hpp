@@ -231,6 +231,45 @@ template <int DIR, typename V> __device__ __forceinline__ void dft32(V* v)
     }
 }
 
+template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v);
+
+// Prime-factor (Good-Thomas) DFT of length N1 N2 with gcd(N1, N2) = 1: no
+// twiddle factors.  Inputs are read at j = (N2 j1 + N1 j2) mod N into an
+// N1 x N2 array, N2 DFTs of length N1 run along j1 and N1 DFTs of length N2
+// along j2, and the result (k1, k2) is X[(E1 k1 + E2 k2) mod N] with
+// E1 = N2 (N2^-1 mod N1) and E2 = N1 (N1^-1 mod N2), because then
+// j k = N2 E1 j1 k1 + N1 E2 j2 k2 (mod N) and N2 E1 = 1 (mod N1),
+// N1 E2 = 1 (mod N2).
+constexpr int inv_mod(int a, int m)
+{
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+template <int DIR, int N1, int N2, typename V> __device__ __forceinline__ void dft_pfa(V* v)
+{
+    constexpr int N = N1 * N2;
+    constexpr int E1 = N2 * inv_mod(N2 % N1, N1), E2 = N1 * inv_mod(N1 % N2, N2);
+    V a[N2][N1];
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2)
+#pragma unroll
+        for (int j1 = 0; j1 < N1; ++j1) a[j2][j1] = v[(N2 * j1 + N1 * j2) % N];
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2) dft<N1, DIR>(a[j2]);
+    V b[N1][N2];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1)
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) b[k1][j2] = a[j2][k1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) dft<N2, DIR>(b[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) v[(E1 * k1 + E2 * k2) % N] = b[k1][k2];
+}
+
 template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
 {
     if constexpr (R == 1) {
@@ -238,6 +277,11 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
     else if constexpr (R == 3) dft3<DIR>(v);
     else if constexpr (R == 4) dft4<DIR>(v);
     else if constexpr (R == 5) dft5<DIR>(v);
+    else if constexpr (R == 6) dft_pfa<DIR, 2, 3>(v);
+    else if constexpr (R == 10) dft_pfa<DIR, 2, 5>(v);
+    else if constexpr (R == 12) dft_pfa<DIR, 4, 3>(v);
+    else if constexpr (R == 15) dft_pfa<DIR, 3, 5>(v);
+    else if constexpr (R == 20) dft_pfa<DIR, 4, 5>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
     else if constexpr (R == 32) dft32<DIR>(v);

@@ -74,7 +74,7 @@ def test_plan_layout_and_query(n, prec):
         assert not info["ready"]
         prod = 1
         for r in info["radices"]:
-            assert r in (2, 3, 4, 5, 8, 16)
+            assert r in (2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20)
             prod *= r
         assert prod == 2 * n
         assert info["radices"][0] == 16
