@@ -18,9 +18,9 @@ template <> struct PlanFor<16, 0> { using Fwd = Radices<16>; using Inv = Radices
 template <> struct PlanFor<32, 0> { using Fwd = Radices<16, 2>; using Inv = Radices<2, 16>; };
 template <> struct PlanFor<48, 0> { using Fwd = Radices<16, 3>; using Inv = Radices<3, 16>; };
 template <> struct PlanFor<64, 0> { using Fwd = Radices<16, 4>; using Inv = Radices<4, 16>; };
-template <> struct PlanFor<96, 0> { using Fwd = Radices<16, 3, 2>; using Inv = Radices<2, 3, 16>; };
+template <> struct PlanFor<96, 0> { using Fwd = Radices<16, 6>; using Inv = Radices<6, 16>; };
 template <> struct PlanFor<128, 0> { using Fwd = Radices<16, 8>; using Inv = Radices<8, 16>; };
-template <> struct PlanFor<192, 0> { using Fwd = Radices<16, 3, 4>; using Inv = Radices<4, 3, 16>; };
+template <> struct PlanFor<192, 0> { using Fwd = Radices<16, 12>; using Inv = Radices<12, 16>; };
 template <> struct PlanFor<256, 0> { using Fwd = Radices<16, 16>; using Inv = Radices<16, 16>; };
 template <> struct PlanFor<384, 0> { using Fwd = Radices<16, 3, 8>; using Inv = Radices<8, 3, 16>; };
 template <> struct PlanFor<512, 0> { using Fwd = Radices<16, 2, 16>; using Inv = Radices<16, 2, 16>; };
