@@ -395,6 +395,52 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
+def widening_leg(torch, S):
+    """Solves beyond the headline configuration: lengths with factors 3 and 5
+    (prime-factor radices), and cells of unequal spacings.  Solve time over
+    20 back-to-back solves (best of three), each checked at a few cells
+    against the oracle's direct sum."""
+    import numpy as np
+    import oracle
+    out = []
+    cases = [(480, "f32", None), (480, "f64", None), (400, "f32", None), (360, "f32", None),
+             (512, "f32", (1.5, 0.5))]
+    for n, prec, sp in cases:
+        dx = 1.0 / n
+        s = S.Solver(n, dx, prec, spacing=None if sp is None else (sp[0] * dx, sp[1] * dx))
+        dt = torch.float64 if prec == "f64" else torch.float32
+        g = torch.Generator(device="cuda").manual_seed(n)
+        rho = torch.rand((n, n, n), generator=g, device="cuda", dtype=torch.float64).to(dt)
+        phi = torch.empty_like(rho)
+        for _ in range(3):
+            s(rho, phi)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                s(rho, phi)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 20)
+        cells = np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [n // 2, 3, n - 2], [7, n // 3, n // 2]])
+        r64 = rho.double().cpu().numpy()
+        if sp is None:
+            ref = oracle.direct_sum_cells(r64, cells, dx)
+        else:
+            ref = oracle.direct_sum_cells3(r64, cells, dx, sp[0] * dx, sp[1] * dx)
+        got = phi.double().cpu().numpy()[cells[:, 0], cells[:, 1], cells[:, 2]]
+        out.append({"n": n, "precision": prec, "radices": s.info()["radices"],
+                    "spacing_over_dx": [1.0, 1.0, 1.0] if sp is None else [1.0, sp[0], sp[1]],
+                    "ms_per_solve": best, "solves_per_s": 1e3 / best,
+                    "sampled_rel_max_err_vs_direct_sum": float(np.abs(got - ref).max() / np.abs(ref).max()),
+                    "cells": len(cells)})
+        del s, rho, phi
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(oracle, n_target: int, n_sample: int):
     """The oracle's full FFT-convolution solve on a smaller grid, timed on
     this host (median of 3), scaled to one solve of the target size by the
@@ -559,6 +605,8 @@ def main() -> int:
                          "profiles/hbm_traffic_counters.json")
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-solve batched leg")
     ap.add_argument("--no-host", action="store_true", help="skip the host-resident (PCIe-inclusive) leg")
+    ap.add_argument("--no-widening", action="store_true",
+                    help="skip the leg of other lengths and cell spacings (480^3, 400^3, 360^3, 512^3 stretched)")
     ap.add_argument("--host-leg-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--nested-steps", type=int, default=200, help="steps of the nested leg (0 skips it)")
     args = ap.parse_args()
@@ -739,6 +787,10 @@ def main() -> int:
         log("nested leg")
         out["nested"] = nested_leg(torch, S, side_prec, args.nested_steps, args.warmup)
         torch.cuda.empty_cache()
+
+    if not args.no_widening:
+        log("widening leg")
+        out["widening"] = widening_leg(torch, S)
 
     if not args.no_host:
         # HIP multiplexes streams onto GPU_MAX_HW_QUEUES hardware queues; after
