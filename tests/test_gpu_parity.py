@@ -2,7 +2,7 @@
 
 Tolerances: rel-L2 <= 1e-12 for double-precision plans and <= 1e-6 for
 single-precision plans, with the max-norm error reported beside it.  A
-single-precision plan reads the density rounded to float32, so it is judged
+single-precision plan reads the density rounded to float32, so it is compared
 against the oracle run on that same rounded density (input rounding is not
 solver error).
 """
