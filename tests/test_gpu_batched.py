@@ -52,6 +52,22 @@ def test_batch_matches_single_solves(prec):
         assert err <= tol, (n, err)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_of_five_smooth_lengths(prec):
+    # radices 5, 3 x 3, 10, 15, 6, 12, 20 inside one batch, two members per length
+    sizes = [40, 72, 80, 120, 144, 40, 96, 160, 120, 72]
+    solvers, rhos = _make(prec, sizes, 4200)
+    eager = [s(r) for s, r in zip(solvers, rhos)]
+    outs = S.solve_batched(solvers, rhos)
+    torch.cuda.synchronize()
+    for n, a, b in zip(sizes, outs, eager):
+        assert torch.equal(a, b), n
+    tol = 1e-12 if prec == "f64" else 1e-6
+    for n, a, r in zip(sizes[:5], outs[:5], rhos[:5]):
+        ref = oracle.fft_conv(r.double().cpu().numpy(), 1.0 / n)
+        assert oracle.rel_l2(a.double().cpu().numpy(), ref) <= tol, n
+
+
 def test_batch_with_large_member():
     # two n = 256 members share one launch of the persistent z pass (FP32 default there)
     sizes = [256, 32, 64, 128, 256]
