@@ -143,7 +143,7 @@ def test_five_smooth_sizes_match_oracle(prec, n):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("n", [216, 240, 288, 320, 360, 400, 432, 480])
+@pytest.mark.parametrize("n", [192, 216, 240, 288, 320, 360, 384, 400, 432, 480])
 def test_five_smooth_large_sampled_direct_sum(prec, n):
     rho = inputs.make_density(n, 24, 800 + n, sigma=(0.01, 0.05), noise=1e-3)
     got, rho_used, s = gpu_solve(rho, prec)
