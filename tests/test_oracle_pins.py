@@ -332,3 +332,46 @@ def test_anisotropic_monopole_far_field(oracle_lib):
     for (a, b, c) in [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1)]:
         r = math.sqrt((z[a, b, c] - cz) ** 2 + (y[a, b, c] - cy) ** 2 + (x[a, b, c] - cx) ** 2)
         assert abs(phi[a, b, c] + mass / r) <= 2e-3 * mass / r
+
+
+# --------------------------------------------------------------------------
+# Worked examples stored in tests/golden (definition and closed forms).
+# --------------------------------------------------------------------------
+
+def _golden_cases():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "worked_examples.txt")
+    cases = []
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        name, *pairs = line.split()
+        cases.append((name, dict(p.split("=", 1) for p in pairs)))
+    return cases
+
+
+@pytest.mark.parametrize("name,kv", _golden_cases())
+def test_golden_worked_examples(oracle_lib, name, kv):
+    f = {k: float(v) for k, v in kv.items() if k not in ("n", "di", "dj", "dk", "cell")}
+    want = f["expect"]
+    if name.startswith("single_cell"):
+        rho = np.full((1, 1, 1), f["rho"])
+        got = [oracle_lib.direct_sum(rho, f["dx"], G=f["G"], self_coeff=f["self_coeff"])[0, 0, 0],
+               oracle_lib.fft_conv(rho, f["dx"], G=f["G"], self_coeff=f["self_coeff"])[0, 0, 0]]
+    elif name == "kernel_345":
+        got = [oracle_lib.kernel_value(int(kv["di"]), int(kv["dj"]), int(kv["dk"]), f["dx"])]
+    elif name == "kernel_box_122":
+        got = [oracle_lib.kernel_value3(int(kv["di"]), int(kv["dj"]), int(kv["dk"]), f["dx"], f["dy"], f["dz"])]
+    elif name == "unit_cube_average":
+        got = [oracle_lib.cell_average_inv_r(f["a"], f["b"], f["c"])]
+    elif name == "impulse_2cube":
+        n, dx = int(kv["n"]), f["dx"]
+        rho = np.zeros((n, n, n))
+        rho[0, 0, 0] = 1.0 / dx ** 3
+        z, y, x = (int(c) for c in kv["cell"].split(","))
+        got = [oracle_lib.direct_sum(rho, dx)[z, y, x], oracle_lib.fft_conv(rho, dx)[z, y, x]]
+    else:
+        raise AssertionError(f"unknown golden case {name}")
+    for g in got:
+        assert abs(g - want) <= 1e-14 * abs(want), (name, g, want)
