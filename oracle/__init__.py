@@ -17,6 +17,10 @@ ctypes.  Functions:
   :func:`kernel_pad3`, :func:`kernel_value3` -- the same on cells of spacings
   dx, dy, dz (x, y, z); :func:`cell_average_inv_r` -- the self-cell average
   of 1/|r| over such a cell
+* :func:`direct_sum_box`, :func:`direct_sum_cells_box`, :func:`fft_conv_box`,
+  :func:`kernel_pad_box`, :func:`fft3_box` -- boxes of nx x ny x nz cells
+  (arrays [z][y][x]) with spacings dx, dy, dz, each axis padded to twice its
+  own length
 
 Kernel: K(d) = -1/(dx |d|) for d != 0, K(0) = -self_coeff/dx (default 2.38).
 On dx x dy x dz cells: K(d) = -1/|(di dx, dj dy, dk dz)| and, unless the cell
@@ -72,6 +76,11 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "or_direct_sum_cells3": ([i, d, d, d, d, d, dp, i, ip, dp], i),
         "or_kernel_pad3": ([i, d, d, d, d, dp], i),
         "or_fft_conv3": ([i, d, d, d, d, d, dp, dp], i),
+        "or_direct_sum_box": ([i, i, i, d, d, d, d, d, dp, dp], i),
+        "or_direct_sum_cells_box": ([i, i, i, d, d, d, d, d, dp, i, ip, dp], i),
+        "or_fft3_box": ([i, i, i, dp, i], i),
+        "or_kernel_pad_box": ([i, i, i, d, d, d, d, dp], i),
+        "or_fft_conv_box": ([i, i, i, d, d, d, d, d, dp, dp], i),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -220,6 +229,57 @@ class Oracle:
         _check(self.lib.or_fft_conv3(rho.shape[0], dx, dy, dz, G, self_coeff, _dp(rho), _dp(phi)), "fft_conv3")
         return phi
 
+    # boxes of nx x ny x nz cells (arrays [z][y][x]) with spacings dx, dy, dz
+    @staticmethod
+    def _box(rho: np.ndarray) -> np.ndarray:
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        if rho.ndim != 3:
+            raise ValueError("rho must be a 3D [z][y][x] array")
+        return rho
+
+    def direct_sum_box(self, rho: np.ndarray, dx: float, dy: float, dz: float, G: float = 1.0,
+                       self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = self._box(rho)
+        nz, ny, nx = rho.shape
+        phi = np.empty_like(rho)
+        _check(self.lib.or_direct_sum_box(nx, ny, nz, dx, dy, dz, G, self_coeff, _dp(rho), _dp(phi)),
+               "direct_sum_box")
+        return phi
+
+    def direct_sum_cells_box(self, rho: np.ndarray, cells: Sequence[Sequence[int]], dx: float, dy: float,
+                             dz: float, G: float = 1.0, self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = self._box(rho)
+        nz, ny, nx = rho.shape
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+        out = np.empty(c.shape[0], dtype=np.float64)
+        rc = self.lib.or_direct_sum_cells_box(nx, ny, nz, dx, dy, dz, G, self_coeff, _dp(rho), int(c.shape[0]),
+                                              c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out))
+        _check(rc, "direct_sum_cells_box")
+        return out
+
+    def fft3_box(self, a: np.ndarray, sign: int = -1) -> np.ndarray:
+        a = np.ascontiguousarray(a, dtype=np.complex128).copy()
+        if a.ndim != 3:
+            raise ValueError("a must be a 3D [z][y][x] array")
+        pz, py, px = a.shape
+        _check(self.lib.or_fft3_box(px, py, pz, _dp(a.view(np.float64)), int(sign)), "fft3_box")
+        return a
+
+    def kernel_pad_box(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
+                       self_coeff: float = SELF_COEFF) -> np.ndarray:
+        k = np.empty((2 * nz, 2 * ny, 2 * nx), dtype=np.float64)
+        _check(self.lib.or_kernel_pad_box(nx, ny, nz, dx, dy, dz, self_coeff, _dp(k)), "kernel_pad_box")
+        return k
+
+    def fft_conv_box(self, rho: np.ndarray, dx: float, dy: float, dz: float, G: float = 1.0,
+                     self_coeff: float = SELF_COEFF) -> np.ndarray:
+        rho = self._box(rho)
+        nz, ny, nx = rho.shape
+        phi = np.empty_like(rho)
+        _check(self.lib.or_fft_conv_box(nx, ny, nz, dx, dy, dz, G, self_coeff, _dp(rho), _dp(phi)),
+               "fft_conv_box")
+        return phi
+
     @staticmethod
     def rel_l2(a, ref):
         return rel_l2(a, ref)
@@ -260,6 +320,11 @@ direct_sum3 = _default.direct_sum3
 direct_sum_cells3 = _default.direct_sum_cells3
 kernel_pad3 = _default.kernel_pad3
 fft_conv3 = _default.fft_conv3
+direct_sum_box = _default.direct_sum_box
+direct_sum_cells_box = _default.direct_sum_cells_box
+fft3_box = _default.fft3_box
+kernel_pad_box = _default.kernel_pad_box
+fft_conv_box = _default.fft_conv_box
 
 
 def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:

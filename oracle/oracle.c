@@ -38,6 +38,11 @@
  * Sign convention: forward uses exp(-2 pi i jk / n), inverse exp(+2 pi i jk / n),
  * neither normalised.
  *
+ * Boxes of nx x ny x nz cells (the "_box" routines: or_direct_sum_box,
+ * or_direct_sum_cells_box, or_kernel_pad_box, or_fft3_box, or_fft_conv_box)
+ * take the same definition with one length per axis; the convolution pads
+ * each axis to twice its own length.
+ *
  * Cells with spacings dx, dy, dz along x, y, z (the "3" routines): the
  * displacement length is |(di dx, dj dy, dk dz)|, the volume factor dx dy dz,
  * and the self cell takes the cell average of 1/|r| over the dx x dy x dz
@@ -521,6 +526,190 @@ int or_fft_conv3(int n, double dx, double dy, double dz, double g, double self_c
     if (!k) return OR_ERR_NOMEM;
     int rc = or_kernel_pad3(n, dx, dy, dz, self_coeff, k);
     if (!rc) rc = conv_core(n, MUT(13) ? g * dx * dx * dx : g * dx * dy * dz, k, rho, phi);
+    free(k);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Boxes of nx x ny x nz cells (x, y, z) with spacings dx, dy, dz: the same
+ * definition with a separate length per axis, and the convolution theorem
+ * with each axis padded to twice its own length.
+ * ------------------------------------------------------------------------- */
+
+static int bad_box(int nx, int ny, int nz) { return nx <= 0 || ny <= 0 || nz <= 0; }
+
+/* Table of K over non-negative displacements, index [az][ay][ax]. */
+static double *kernel_table_box(int nx, int ny, int nz, double dx, double dy, double dz, double self_coeff)
+{
+    double *k = (double *)malloc((size_t)nx * ny * nz * sizeof(double));
+    if (!k) return NULL;
+    for (int a = 0; a < nz; ++a)
+        for (int b = 0; b < ny; ++b)
+            for (int c = 0; c < nx; ++c)
+                k[((size_t)a * ny + b) * nx + c] = or_kernel_value3(c, b, a, dx, dy, dz, self_coeff);
+    return k;
+}
+
+/* One output cell of the box sum: x-rows summed directly, row sums combined
+ * with Neumaier's compensated summation (as direct_one). */
+static double direct_one_box(int nx, int ny, int nz, const double *ktab, const double *rho, int iz, int iy, int ix)
+{
+    double sum = 0.0, comp = 0.0;
+    for (int jz = 0; jz < nz; ++jz) {
+        const int az = abs(iz - jz);
+        for (int jy = 0; jy < ny; ++jy) {
+            const int ay = abs(iy - jy);
+            const double *kr = ktab + ((size_t)az * ny + ay) * nx;
+            const double *rr = rho + ((size_t)jz * ny + jy) * nx;
+            double row = 0.0;
+            for (int jx = 0; jx < nx; ++jx) row += kr[abs(ix - jx)] * rr[jx];
+            const double t = sum + row;
+            if (fabs(sum) >= fabs(row)) comp += (sum - t) + row;
+            else comp += (row - t) + sum;
+            sum = t;
+        }
+    }
+    return sum + comp;
+}
+
+/* phi = G dx dy dz sum_j K(i-j) rho[j] on all cells of the box; rho, phi: [z][y][x]. */
+int or_direct_sum_box(int nx, int ny, int nz, double dx, double dy, double dz, double g, double self_coeff,
+                      const double *rho, double *phi)
+{
+    if (bad_box(nx, ny, nz) || bad_spacing(dx, dy, dz) || !rho || !phi) return OR_ERR_ARG;
+    double *ktab = kernel_table_box(nx, ny, nz, dx, dy, dz, self_coeff);
+    if (!ktab) return OR_ERR_NOMEM;
+    const double scale = g * dx * dy * dz;
+    const long m = (long)nx * ny * nz;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long c = 0; c < m; ++c) {
+        const int iz = (int)(c / ((long)nx * ny)), iy = (int)((c / nx) % ny), ix = (int)(c % nx);
+        phi[c] = scale * direct_one_box(nx, ny, nz, ktab, rho, iz, iy, ix);
+    }
+    free(ktab);
+    return OR_OK;
+}
+
+/* The box sum at a list of cells (z, y, x). */
+int or_direct_sum_cells_box(int nx, int ny, int nz, double dx, double dy, double dz, double g, double self_coeff,
+                            const double *rho, int ncells, const int *cells, double *out)
+{
+    if (bad_box(nx, ny, nz) || bad_spacing(dx, dy, dz) || !rho || !out || ncells < 0 || (ncells > 0 && !cells))
+        return OR_ERR_ARG;
+    for (int c = 0; c < ncells; ++c)
+        if (cells[3 * c] < 0 || cells[3 * c] >= nz || cells[3 * c + 1] < 0 || cells[3 * c + 1] >= ny ||
+            cells[3 * c + 2] < 0 || cells[3 * c + 2] >= nx)
+            return OR_ERR_ARG;
+    double *ktab = kernel_table_box(nx, ny, nz, dx, dy, dz, self_coeff);
+    if (!ktab) return OR_ERR_NOMEM;
+    const double scale = g * dx * dy * dz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < ncells; ++c)
+        out[c] = scale * direct_one_box(nx, ny, nz, ktab, rho, cells[3 * c], cells[3 * c + 1], cells[3 * c + 2]);
+    free(ktab);
+    return OR_OK;
+}
+
+/* DFT of a px x py x pz box a[z][y][x] (complex, in place), one axis at a
+ * time on gathered pencils, each axis with its own length. */
+static int fft3_box_inplace(int px, int py, int pz, cplx *a, int sign)
+{
+    const int len[3] = {px, py, pz};
+    const long stride[3] = {1, px, (long)px * py};
+    int err = 0;
+    for (int axis = 0; axis < 3 && !err; ++axis) {
+        const int L = len[axis];
+        cplx *tw = twiddle_table(L, sign);
+        if (!tw) return OR_ERR_NOMEM;
+        /* the two other axes, o1 the faster one */
+        const int o1 = axis == 0 ? 1 : 0, o2 = axis == 2 ? 1 : 2;
+        const long npen = (long)len[o1] * len[o2];
+#pragma omp parallel
+        {
+            cplx *g = (cplx *)malloc((size_t)L * sizeof(cplx));
+            cplx *r = (cplx *)malloc((size_t)L * sizeof(cplx));
+            cplx *s = (cplx *)malloc((size_t)L * sizeof(cplx));
+            if (!g || !r || !s) {
+#pragma omp atomic write
+                err = 1;
+            } else {
+#pragma omp for schedule(static)
+                for (long q = 0; q < npen; ++q) {
+                    const long base = (q % len[o1]) * stride[o1] + (q / len[o1]) * stride[o2];
+                    for (int t = 0; t < L; ++t) g[t] = a[base + t * stride[axis]];
+                    fft_rec(L, g, 1, r, s, tw, L);
+                    for (int t = 0; t < L; ++t) a[base + t * stride[axis]] = r[t];
+                }
+            }
+            free(g); free(r); free(s);
+        }
+        free(tw);
+    }
+    return err ? OR_ERR_NOMEM : OR_OK;
+}
+
+/* Box DFT, interleaved complex in place, a[z][y][x] of pz x py x px. */
+int or_fft3_box(int px, int py, int pz, double *data, int sign)
+{
+    if (bad_box(px, py, pz) || !data || (sign != 1 && sign != -1)) return OR_ERR_ARG;
+    return fft3_box_inplace(px, py, pz, (cplx *)data, sign);
+}
+
+/* kpad[z][y][x] = K(min(x,Px-x), min(y,Py-y), min(z,Pz-z)), Pa = 2 Na per axis. */
+int or_kernel_pad_box(int nx, int ny, int nz, double dx, double dy, double dz, double self_coeff, double *kpad)
+{
+    if (bad_box(nx, ny, nz) || bad_spacing(dx, dy, dz) || !kpad) return OR_ERR_ARG;
+    const long px = 2L * nx, py = 2L * ny, pz = 2L * nz;
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < pz; ++z)
+        for (long y = 0; y < py; ++y)
+            for (long x = 0; x < px; ++x) {
+                const long az = z < pz - z ? z : pz - z, ay = y < py - y ? y : py - y, ax = x < px - x ? x : px - x;
+                kpad[(z * py + y) * px + x] = MUT(15) ? or_kernel_value3(ax, az, ay, dx, dy, dz, self_coeff)
+                                                      : or_kernel_value3(ax, ay, az, dx, dy, dz, self_coeff);
+            }
+    return OR_OK;
+}
+
+/* The FFT-convolution solve on a box: both operands zero-padded to
+ * 2nx x 2ny x 2nz, full complex DFTs, product, inverse divided by the padded
+ * size, real part, crop, times G dx dy dz. */
+int or_fft_conv_box(int nx, int ny, int nz, double dx, double dy, double dz, double g, double self_coeff,
+                    const double *rho, double *phi)
+{
+    if (bad_box(nx, ny, nz) || bad_spacing(dx, dy, dz) || !rho || !phi) return OR_ERR_ARG;
+    const long px = 2L * nx, py = 2L * ny, pz = 2L * nz, m = px * py * pz;
+    double *kp = (double *)malloc((size_t)m * sizeof(double));
+    cplx *a = (cplx *)calloc((size_t)m, sizeof(cplx));
+    cplx *k = (cplx *)malloc((size_t)m * sizeof(cplx));
+    if (!kp || !a || !k) {
+        free(kp); free(a); free(k);
+        return OR_ERR_NOMEM;
+    }
+    int rc = or_kernel_pad_box(nx, ny, nz, dx, dy, dz, self_coeff, kp);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < m; ++i) k[i] = kp[i];
+    free(kp);
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < nz; ++z)
+        for (long y = 0; y < ny; ++y)
+            for (long x = 0; x < nx; ++x) a[(z * py + y) * px + x] = rho[(z * ny + y) * nx + x];
+    if (!rc) rc = fft3_box_inplace((int)px, (int)py, (int)pz, k, -1);
+    if (!rc) rc = fft3_box_inplace((int)px, (int)py, (int)pz, a, -1);
+    if (!rc) {
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < m; ++i) a[i] *= k[i];
+        rc = fft3_box_inplace((int)px, (int)py, (int)pz, a, +1);
+    }
+    if (!rc) {
+        const double scale = g * dx * dy * dz / (double)(MUT(14) ? px * px * pz : m);
+#pragma omp parallel for schedule(static)
+        for (long z = 0; z < nz; ++z)
+            for (long y = 0; y < ny; ++y)
+                for (long x = 0; x < nx; ++x)
+                    phi[(z * ny + y) * nx + x] = scale * creal(a[(z * py + y) * px + x]);
+    }
+    free(a);
     free(k);
     return rc;
 }

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_box as box
 import test_oracle_pins as pins
 
 MUTATIONS = {
@@ -26,6 +27,8 @@ MUTATIONS = {
     11: "box self cell ignores the spacings",
     12: "y and z spacings swapped in the kernel on dx x dy x dz cells",
     13: "dx^3 instead of dx dy dz as the cell volume",
+    14: "box convolution normalised by Px Px Pz instead of Px Py Pz",
+    15: "y and z displacements exchanged in the padded box kernel",
 }
 
 CHECKS = [
@@ -40,6 +43,8 @@ CHECKS = [
     lambda o: pins.test_box_self_cell_scales_like_the_cube(o),
     lambda o: pins.test_anisotropic_impulse_response_and_axis_swap(o),
     lambda o: pins.test_anisotropic_monopole_far_field(o),
+    lambda o: box.test_box_fft_conv_equals_direct_sum(o, (6, 10, 8), (0.1, 0.13, 0.07)),
+    lambda o: box.test_box_kernel_pad_is_even_per_axis(o),
 ]
 
 
