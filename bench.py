@@ -139,25 +139,34 @@ def step_percentiles(torch, fn, k):
     return {"p10_ms": float(q[0]), "p50_ms": float(q[1]), "p90_ms": float(q[2]), "samples": k}
 
 
-def copy_rate(torch, nbytes=2 << 30, reps=10):
-    """HBM rate of a plain device copy (bytes read + written per second), the
-    achievable-bandwidth reference for the byte-model rates."""
+def copy_rate(torch, S, nbytes=2 << 30, reps=10):
+    """HBM rate (bytes read + written per second) of the library's plain
+    streaming copy kernel (ps_stream_copy: 16-byte items, eight loads in
+    flight per thread) on the stream it is launched on: the achievable
+    bandwidth against which the pass rates are read.  torch's copy_ of the
+    same buffers is timed beside it."""
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 2.0 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+    own = timed(lambda: S.ps_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, stream))
+    lib = timed(lambda: b.copy_(a))
     del a, b
     torch.cuda.empty_cache()
-    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+    return {"GBps": own, "kernel": "ps_stream_copy", "bytes_each_way": nbytes, "torch_copy_GBps": lib}
 
 
 def make_solver(S, n, prec):
@@ -259,11 +268,25 @@ def batched_leg(torch, S, prec, steps, warmup):
     rb = 8 if prec == "f64" else 4
     b2 = sum(model_bytes(n, rb)["B2"] for n in sizes)
     hist = {str(n): sizes.count(n) for n in sorted(set(sizes))}
+    # each size group alone, as its own batched call replayed from a graph
+    groups = {}
+    for n in sorted(set(sizes)):
+        idx = [i for i, m in enumerate(sizes) if m == n]
+        sv, rv, ov = [solvers[i] for i in idx], [rhos[i] for i in idx], [outs[i] for i in idx]
+        S.solve_batched(sv, rv, ov)
+        torch.cuda.synchronize()
+        gg = _graph_of(torch, lambda sv=sv, rv=rv, ov=ov: S.solve_batched(sv, rv, ov))
+        gms = _time_replays(torch, gg, steps, warmup)
+        gb2 = len(idx) * model_bytes(n, rb)["B2"]
+        groups[str(n)] = {"solves": len(idx), "ms": gms, "B2_bytes": gb2, "effective_GBps_B2": gb2 / (gms * 1e-3) / 1e9,
+                          "frac_of_peak_B2": gb2 / (gms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        del gg
     return {"workload": "96 solves, N in {32,48,64,96,128} (seeded), 4-32 blobs each, one batched solve (per pass one launch per size group), "
                         "replayed from a captured graph",
             "precision": prec, "sizes": hist, "ms_per_batch": ms, "solves_per_s": 96.0 / (ms * 1e-3),
             "replay_ms": pct,
             "B2_bytes_per_batch": b2, "effective_GBps_B2": b2 / (ms * 1e-3) / 1e9,
+            "frac_of_peak_B2": b2 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "size_groups_alone": groups,
             "max_rel_l2_vs_single_solves": worst, "rel_l2_vs_oracle_smallest": oerr}
 
 
@@ -325,6 +348,7 @@ def nested_leg(torch, S, prec, nsteps, warmup):
             "solves_per_s": 3 * nsteps / (ms_seq * 1e-3),
             "step_latency_ms_p50": float(np.percentile(lat, 50)), "step_latency_ms_p99": float(np.percentile(lat, 99)),
             "B2_bytes_per_step": b2, "effective_GBps_B2_latency_p50": b2 / (np.percentile(lat, 50) * 1e-3) / 1e9,
+            "frac_of_peak_B2_latency_p50": b2 / (np.percentile(lat, 50) * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "max_rel_l2_vs_single_solves": worst}
 
 
@@ -441,48 +465,103 @@ def widening_leg(torch, S):
     return out
 
 
-def cpu_baseline(oracle, n_target: int, n_sample: int):
-    """The oracle's full FFT-convolution solve on a smaller grid, timed on
-    this host (median of 3), scaled to one solve of the target size by the
-    ratio of FFT work P^3 log2 P (the oracle's cost is dominated by its 1D FFT
-    passes); plus one run on a single core at half that size."""
-    import math
-    from paper_2409_02294_amd import inputs
+def host_memory_kib():
+    """MemTotal and MemAvailable of this host, KiB."""
+    out = {}
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                k, v = line.split(":", 1)
+                if k in ("MemTotal", "MemAvailable"):
+                    out[k] = int(v.split()[0])
+    except OSError:
+        pass
+    return out
 
-    def timed(ns, reps):
-        rho = inputs.make_density(ns, 64, 1002, sigma=(0.01, 0.05), noise=1e-3)
-        ts = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            oracle.fft_conv(rho, 1.0 / ns)
-            ts.append(time.perf_counter() - t0)
-        ts.sort()
-        return ts[len(ts) // 2]
+
+def oracle_bytes(n: int) -> int:
+    """Host memory of one oracle FFT-convolution solve at n^3: the padded
+    kernel (P^3 doubles), the padded density and kernel spectrum (two P^3
+    complex arrays), the density and potential (n^3 doubles each)."""
+    p = 2 * n
+    return p ** 3 * 8 + 2 * p ** 3 * 16 + 2 * n ** 3 * 8
+
+
+def cpu_oracle_child(n: int, reps: int) -> dict:
+    """One child-process leg of the CPU baseline: `reps` full oracle solves at
+    n^3 (FFT convolution, FP64) on the threads this process may use, bound by
+    the OpenMP settings the parent put in the environment."""
+    import oracle
+    from paper_2409_02294_amd import inputs
+    mem = host_memory_kib()
+    need = oracle_bytes(n)
+    if mem.get("MemAvailable", 0) * 1024 < 1.2 * need:
+        return {"n": n, "skipped": f"needs {need / 2**30:.1f} GiB, {mem.get('MemAvailable', 0) / 2**20:.1f} GiB available"}
+    rho = inputs.make_density(n, 256 if n == 512 else 64, 1003 if n == 512 else 1002, sigma=(0.01, 0.05), noise=1e-3)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        oracle.fft_conv(rho, 1.0 / n)
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return {"n": n, "seconds": ts[len(ts) // 2], "runs": reps, "threads": oracle.get_threads(),
+            "omp": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OMP_PROC_BIND", "OMP_PLACES")}}
+
+
+def cpu_baseline(n_target: int) -> dict:
+    """The FP64 CPU oracle timed on this host's cores in child processes with
+    OpenMP threads bound to cores (OMP_PROC_BIND=close, OMP_PLACES=cores):
+    one full oracle solve at the target size when the host has the memory
+    (measured, not scaled), else solves at half the size scaled by the FFT-work
+    ratio P^3 log2 P (labelled as an extrapolation); plus one single-thread
+    solve at an eighth of the size, scaled the same way."""
+    import math
+    import subprocess
+
+    def child(n, reps, threads=None):
+        env = dict(os.environ, OMP_PROC_BIND="close", OMP_PLACES="cores")
+        if threads:
+            env["OMP_NUM_THREADS"] = str(threads)
+        elif "OMP_NUM_THREADS" not in env:
+            env["OMP_NUM_THREADS"] = str(len(os.sched_getaffinity(0)))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-only", str(n), "--steps",
+                            str(reps)], capture_output=True, text=True, timeout=600, env=env)
+        if r.returncode != 0:
+            return {"n": n, "error": r.stderr.strip()[-300:]}
+        return json.loads(r.stdout.strip().splitlines()[-1])
 
     def ratio(ns):
         pt, ps = 2 * n_target, 2 * ns
         return (pt ** 3 * math.log2(pt)) / (ps ** 3 * math.log2(ps))
 
-    threads = oracle.get_threads()
-    t = timed(n_sample, 3)
-    n1 = max(16, n_sample // 2)
-    oracle.set_threads(1)
-    try:
-        t1 = timed(n1, 1)
-    finally:
-        oracle.set_threads(threads)
-    return {
-        "value": 1.0 / (t * ratio(n_sample)),
-        "unit": "solves/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": (f"full oracle fft_conv solves at {n_sample}^3 (padded {2 * n_sample}^3, FP64, OpenMP, "
-                   f"{threads} threads): median of 3 = {t:.2f} s; scaled to {n_target}^3 by the FFT-work ratio "
-                   f"{ratio(n_sample):.2f}"),
-        "host_cpu": host_cpu_model(),
-        "one_core": {"value": 1.0 / (t1 * ratio(n1)), "unit": "solves/s",
-                     "sample": f"one solve at {n1}^3 on 1 thread: {t1:.2f} s, scaled by {ratio(n1):.1f}"},
+    mem = host_memory_kib()
+    full = child(n_target, 1)
+    if "seconds" in full:
+        value, kind = 1.0 / full["seconds"], "measured"
+        sample = (f"one full oracle solve at {n_target}^3 (padded {2 * n_target}^3, FP64 FFT convolution, OpenMP, "
+                  f"{full['threads']} threads bound to cores): {full['seconds']:.1f} s")
+        threads = full["threads"]
+    else:
+        half = child(n_target // 2, 3)
+        if "seconds" not in half:
+            return {"error": f"{full} / {half}"}
+        value, kind = 1.0 / (half["seconds"] * ratio(n_target // 2)), "extrapolated"
+        sample = (f"full oracle solves at {n_target // 2}^3 (median of 3, {half['threads']} threads bound to cores): "
+                  f"{half['seconds']:.2f} s, scaled to {n_target}^3 by the FFT-work ratio {ratio(n_target // 2):.2f} "
+                  f"(the {n_target}^3 solve was not run: {full.get('skipped') or full.get('error')})")
+        threads = half["threads"]
+    one = child(max(16, n_target // 8), 1, threads=1)
+    res = {
+        "value": value, "unit": "solves/s", "cores": threads, "kind": "oracle", "sample": sample,
+        "measurement": kind, "host_cpu": host_cpu_model(),
+        "host_MemTotal_GiB": mem.get("MemTotal", 0) / 2 ** 20,
+        "oracle_GiB_at_target": oracle_bytes(n_target) / 2 ** 30,
     }
+    if "seconds" in one:
+        n1 = one["n"]
+        res["one_core"] = {"value": 1.0 / (one["seconds"] * ratio(n1)), "unit": "solves/s",
+                           "sample": f"one solve at {n1}^3 on 1 thread: {one['seconds']:.2f} s, scaled by {ratio(n1):.1f}"}
+    return res
 
 
 COPY_ELEMS = 1 << 28  # float32 elements of the counter-scaling copy (1 GiB read, 1 GiB written)
@@ -608,11 +687,16 @@ def main() -> int:
     ap.add_argument("--no-widening", action="store_true",
                     help="skip the leg of other lengths and cell spacings (480^3, 400^3, 360^3, 512^3 stretched)")
     ap.add_argument("--host-leg-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-oracle-only", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--nested-steps", type=int, default=200, help="steps of the nested leg (0 skips it)")
     args = ap.parse_args()
 
     if args.ingest_counters:
         return ingest_counters(args)
+    if args.cpu_oracle_only:
+        # a child of the CPU-baseline leg: no GPU, threads bound by the parent's environment
+        print(json.dumps(cpu_oracle_child(args.cpu_oracle_only, args.steps)), flush=True)
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -643,7 +727,6 @@ def main() -> int:
     phis = {}
     head = args.precision
     precs = [head] + [p for p in args.compare.split(",") if p and p != head]
-    pass_ms = None
     for prec in precs:
         log(f"timing {prec}")
         try:
@@ -664,12 +747,13 @@ def main() -> int:
             rec["label"] = "split-bf16 with three product terms: reported, does not meet the 1e-6 bound"
         if not prec.endswith("plain"):
             rec["variants"] = s.info()["variant"]
+            pms = time_passes(torch, S, s, rho, phi, max(3, steps // 2))
+            pb = pass_bytes(n, 8 if prec.startswith("f64") else 4)
+            rec["pass_ms"] = dict(zip(PASS_NAMES, pms))
+            rec["pass_GBps"] = {k: pb[k] / (t * 1e-3) / 1e9 for k, t in zip(PASS_NAMES, pms)}
+            s(rho, phi)
         if prec == head:
             rec["step_ms"] = step_percentiles(torch, lambda: s(rho, phi), max(20, steps))
-        if prec == head and not prec.endswith("plain"):
-            pass_ms = time_passes(torch, S, s, rho, phi, max(3, steps // 2))
-            rec["pass_ms"] = dict(zip(PASS_NAMES, pass_ms))
-            s(rho, phi)
         torch.cuda.synchronize()
         phis[prec] = (phi.double().cpu().numpy(), rho.double().cpu().numpy())
         results[prec] = rec
@@ -702,6 +786,12 @@ def main() -> int:
                         f"{'256' if n == 512 else '64'} Gaussian blobs + 1e-3 noise, resident in HBM",
             "n": n, "padded": 2 * n, "precision": head,
         },
+        "headline_precision": {
+            "f32": "PS_F32: FP32 arithmetic with every DFT on the vector ALUs (kernel and twiddles built in FP64, "
+                   "rounded once); no narrower than the split form, which is timed beside it under others.f32_split",
+            "f32_split": "PS_F32_SPLIT: FP32 storage, radix-16 DFTs as split-bf16 matrix-core products (six terms)",
+            "f64": "PS_F64: FP64 throughout",
+        }.get(head, head),
         "step_ms": hr.get("step_ms"),
         "effective_GBps_B2": models["B2"] / (ms * 1e-3) / 1e9,
         "frac_of_peak_B2": models["B2"] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
@@ -710,40 +800,41 @@ def main() -> int:
         "others": {k: v for k, v in results.items() if k != head},
         "input_generation_s": gen_s,
     }
-    if pass_ms is not None:
+    if "pass_ms" in hr:
+        pass_ms = [hr["pass_ms"][k] for k in PASS_NAMES]
         pb = pass_bytes(n, rb)
         dom = max(range(5), key=lambda k: pass_ms[k])
         kname = PASS_NAMES[dom]
         ach = pb[kname] / (pass_ms[dom] * 1e-3) / 1e9
         out["pass_ms"] = hr["pass_ms"]
-        out["pass_GBps"] = {PASS_NAMES[k]: pb[PASS_NAMES[k]] / (pass_ms[k] * 1e-3) / 1e9 for k in range(5)}
+        out["pass_GBps"] = hr["pass_GBps"]
         traffic = measured_traffic(kname, n, head, hr["variants"][dom])
+        out["roofline"] = {
+            "kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": pb[kname], "avg_launch_ms": pass_ms[dom],
+            "whole_solve_frac_B2": out["frac_of_peak_B2"],
+        }
         if kname == "z_conv":
-            # the fused z pass issues ~1000 vector-ALU instructions per pencil
-            # for 16 KB of HBM traffic: its nearest ceiling is the vector ALU
+            # secondary view: the fused z pass also keeps the vector ALUs busy
             tf = z_flops(n) / (pass_ms[dom] * 1e-3) / 1e12
-            peak = PEAK_VALU_TFLOPS["f64" if rb == 8 else "f32"]
-            out["roofline"] = {
-                "kernel": kname, "bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
-                "frac": tf / peak, "traffic": traffic,
-                "algorithmic_flops_per_launch": z_flops(n), "avg_launch_ms": pass_ms[dom],
-                "peak_nonpacked": PEAK_VALU_NONPACKED_TFLOPS, "frac_nonpacked": tf / PEAK_VALU_NONPACKED_TFLOPS,
-                "hbm_GBps_algorithmic": ach, "hbm_frac_algorithmic": ach / PEAK_HBM_GBS,
-                "algorithmic_bytes_per_launch": pb[kname],
-            }
-        else:
-            out["roofline"] = {
-                "kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": pb[kname], "avg_launch_ms": pass_ms[dom],
+            out["roofline"]["alu_view"] = {
+                "achieved_TFLOPs": tf, "algorithmic_flops_per_launch": z_flops(n),
+                "peak_published_TFLOPs": PEAK_VALU_TFLOPS["f64" if rb == 8 else "f32"],
+                "peak_nonpacked_TFLOPs": PEAK_VALU_NONPACKED_TFLOPS,
+                "frac_nonpacked": tf / PEAK_VALU_NONPACKED_TFLOPS,
             }
     for other in ("f64", "f64_plain"):
         if other in results and "solves_per_s" in results[other]:
             out[f"speedup_vs_{other}"] = hr["solves_per_s"] / results[other]["solves_per_s"]
     if "f32_split" in results and "f64_plain" in results and "solves_per_s" in results["f64_plain"]:
         out["speedup_f32_split_vs_f64_plain"] = results["f32_split"]["solves_per_s"] / results["f64_plain"]["solves_per_s"]
-    out["copy_GBps"] = copy_rate(torch)
-    out["frac_of_copy_B3"] = out["effective_GBps_B3"] / out["copy_GBps"]
+    cp = copy_rate(torch, S)
+    out["copy"] = cp
+    out["copy_GBps"] = cp["GBps"]
+    out["frac_of_copy_B3"] = out["effective_GBps_B3"] / cp["GBps"]
+    if "roofline" in out:
+        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / cp["GBps"]
 
     if not args.no_accuracy:
         import oracle
@@ -777,16 +868,28 @@ def main() -> int:
                 acc[prec]["rel_l2_vs_f64_path"] = float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
                 acc[prec]["rel_max_vs_f64_path"] = float(np.abs(a - ref).max() / np.abs(ref).max())
         out["accuracy"] = acc
+        ha = acc.get(head, {})
+        bound = 1e-12 if head.startswith("f64") else 1e-6
+        worst = max([v for k, v in ha.items() if k in ("rel_l2_vs_f64_path", "sampled_rel_max_err_vs_direct_sum")],
+                    default=None)
+        out["accuracy_bound"] = bound
+        out["accuracy_ok"] = None if worst is None else bool(worst <= bound)
+        if out["accuracy_ok"] is False:
+            log(f"headline {head} exceeds the {bound:g} error bound ({worst:.3e})")
 
-    side_prec = head if head in ("f32", "f64", "f32_split") else "f32"
+    side = [p for p in ("f32_split", "f32") if p in precs] or [head]
     if not args.no_batched:
-        log("batched leg")
-        out["batched"] = batched_leg(torch, S, side_prec, max(5, args.steps), args.warmup)
-        torch.cuda.empty_cache()
+        out["batched"] = {}
+        for prec in side:
+            log(f"batched leg ({prec})")
+            out["batched"][prec] = batched_leg(torch, S, prec, max(5, args.steps), args.warmup)
+            torch.cuda.empty_cache()
     if args.nested_steps > 0:
-        log("nested leg")
-        out["nested"] = nested_leg(torch, S, side_prec, args.nested_steps, args.warmup)
-        torch.cuda.empty_cache()
+        out["nested"] = {}
+        for prec in side:
+            log(f"nested leg ({prec})")
+            out["nested"][prec] = nested_leg(torch, S, prec, args.nested_steps, args.warmup)
+            torch.cuda.empty_cache()
 
     if not args.no_widening:
         log("widening leg")
@@ -799,7 +902,8 @@ def main() -> int:
         # so this leg runs in a child process with only its own streams.
         log("host-resident leg (child process)")
         import subprocess
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--host-leg-only", "--precision", side_prec],
+        hp = head if head in ("f32", "f64", "f32_split") else "f32"
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--host-leg-only", "--precision", hp],
                            capture_output=True, text=True, timeout=300)
         if r.returncode == 0:
             out["host_resident"] = json.loads(r.stdout.strip().splitlines()[-1])
@@ -808,9 +912,8 @@ def main() -> int:
             out["host_resident"] = {"error": r.stderr.strip()[-500:]}
 
     if not args.no_cpu_baseline:
-        import oracle
-        log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(oracle, n, min(n, 256))
+        log("timing the CPU oracle (child processes)")
+        out["cpu_baseline"] = cpu_baseline(n)
 
     print(json.dumps(out), flush=True)
     return 0

@@ -83,9 +83,14 @@ typedef struct {
     int variant[5];         /* kernel variant of each pruned pass (see ps_plan_set_variant) */
     int split_terms;        /* PS_F32_SPLIT: split-bf16 product terms per DFT-16 (6 or 3); else 0 */
     double dy, dz;          /* cell spacings along y and z (dx unless set by ps_plan_set_spacing) */
+    int nx, ny, nz;         /* cells along x, y, z (all n for a cube; n, p, h and radices describe x) */
 } ps_plan_info;
 
-/* Create a plan for an n^3 grid of spacing dx (> 0) in the given precision.
+/* Create a plan for an n^3 grid of spacing dx (> 0) in the given precision:
+ * one mesh level of the convolution method whose potential solve the paper
+ * benchmarks (section 3).  The plan is an opaque host object and every
+ * device buffer it later uses is the caller's, passed by raw address (the
+ * C-bound, caller-owned convention of section 2.2.2 and appendix A).
  * Host work only (radix plan, twiddle tables in double then rounded once to
  * the plan's type, workspace layout); no HIP call.  tune_cache may name a
  * tuning file written by ps_autotune (its choice for this length and
@@ -93,6 +98,22 @@ typedef struct {
  * NULL.  On success *out owns a
  * host object to release with ps_plan_destroy. */
 ps_status ps_plan_create(ps_plan *out, int n, double dx, ps_precision prec, const char *tune_cache);
+
+/* A plan for a box of nx x ny x nz cells (arrays [z][y][x], x fastest) of
+ * spacings dx, dy, dz (> 0): the same solve on a mesh that is not a cube,
+ * phi[i] = G dx dy dz sum_j K(i - j) rho[j] over the box, with each axis
+ * zero-padded to twice its own length (the paper's mesh levels are cubes of
+ * N^3 cells, section 3; this widens them).  K is the kernel of
+ * ps_plan_set_spacing.  Each of nx, ny, nz must be a supported n (else
+ * PS_ERR_UNSUPPORTED).  Equal lengths give exactly the plan of
+ * ps_plan_create (with ps_plan_set_spacing); unequal lengths run the
+ * pruned pipeline's one-tile-per-workgroup kernels for each axis length
+ * (PS_F64, PS_F32, PS_F32_SPLIT; the PLAIN precisions are for cubes,
+ * PS_ERR_UNSUPPORTED) and ignore tune_cache.  Host work only, no HIP call;
+ * every other entry point takes the plan as it takes a cube's, with arrays
+ * of nx ny nz reals. */
+ps_status ps_plan_create_box(ps_plan *out, int nx, int ny, int nz, double dx, double dy, double dz,
+                             ps_precision prec, const char *tune_cache);
 
 /* Bytes of device workspace the plan needs (transformed kernel, tables,
  * intermediates, and the scratch of ps_green_build). */
@@ -102,14 +123,22 @@ ps_status ps_plan_workspace_bytes(ps_plan p, size_t *bytes);
 ps_status ps_plan_query(ps_plan p, ps_plan_info *info);
 
 /* Build the transformed kernel in double precision on the GPU into the
- * caller's workspace and bind that workspace to the plan: uploads the
+ * caller's workspace and bind that workspace to the plan (the
+ * pre-transformed Green's function of the convolution method, section 3;
+ * the paper does not print the kernel, whose values are fixed by the
+ * definition at the top of this file): uploads the
  * twiddle tables, generates K_pad (self cell -self_coeff/dx), transforms it,
  * scales by G dx^3 / P^3 and stores the real octant in the plan's type.
  * Synchronises `stream`.  Must not be called under stream capture
  * (PS_ERR_CAPTURE).  May be called again (new G or workspace). */
 ps_status ps_green_build(ps_plan p, void *d_workspace, double G, double self_coeff, void *stream);
 
-/* One solve: phi = potential of rho, enqueued on `stream`. */
+/* One solve: phi = potential of rho, enqueued on `stream` (the convolution
+ * solve of one mesh level, section 3, whose FFTs section 1 names as the
+ * performance-critical GPU work).  rho and phi are device addresses the
+ * caller owns (section 2.2.2, appendix A).  Errors: PS_ERR_INVALID for NULL,
+ * misaligned or overlapping arrays, PS_ERR_NOT_READY before ps_green_build,
+ * PS_ERR_DEVICE if a launch fails; nothing is enqueued on error. */
 ps_status ps_solve(ps_plan p, const void *d_rho, void *d_phi, void *stream);
 
 /* Bytes of caller-owned device staging memory that ps_solve_host needs for
@@ -119,7 +148,7 @@ ps_status ps_host_stage_bytes(ps_plan p, size_t *bytes);
 
 /* count solves with one plan on host-resident densities: rho[i] -> phi[i],
  * host pointers to n^3 reals in the layout of ps_solve.  The host <-> device
- * copies the paper's section 2.2 measures (pinned against pageable host
+ * copies the paper's section 2.2.1 measures (pinned against pageable host
  * memory) are staged through d_stage (at least ps_host_stage_bytes, 256-byte
  * aligned, two slots per direction) and run on two copy streams that the
  * plan creates (default priority) and keeps until it is destroyed: the
@@ -134,7 +163,10 @@ ps_status ps_host_stage_bytes(ps_plan p, size_t *bytes);
 ps_status ps_solve_host(ps_plan p, const void *const *h_rho, void *const *h_phi, int count, void *d_stage,
                         size_t stage_bytes, void *stream);
 
-/* count (1..1024) independent solves enqueued on `stream`.  Members are
+/* count (1..1024) independent solves enqueued on `stream`: several mesh
+ * levels (or time steps) on one GPU, where the paper gives each nested level
+ * its own GPU and names splitting one GPU among levels as an option it did
+ * not pursue (section 3).  Members are
  * grouped by length and kernel variant; each pass is one launch per group,
  * over the group's members (grid z), with the same kernels ps_solve uses, so
  * a member's result equals ps_solve's for its plan bitwise.  The groups of a
@@ -166,11 +198,13 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * wavefront-owned pencils on the radix-32-based plan (n = 256, 512; else
  * as 1), 3 = persistent workgroups that load the next tile while
  * transforming the current one (radix-32-based plan where it exists, else
- * radix-16-based; not for PS_F32_SPLIT plans), 4 = persistent on the
- * radix-16-based plan with fewer pencils per wavefront (not for
- * PS_F32_SPLIT plans).  Every
- * variant computes the same result to rounding.  PS_F32_SPLIT plans keep the
- * radix-16-based plan (variants 0 and 0/1 only); for them "pass" 5 sets the
+ * radix-16-based), 4 = persistent on the radix-16-based plan with fewer
+ * pencils per wavefront.  Boxes (ps_plan_create_box with unequal lengths)
+ * run the one-tile-per-workgroup variants only: y passes 0 and 1, z pass 0,
+ * 1 and 2 (PS_ERR_UNSUPPORTED otherwise); the radix-32-based plan follows
+ * the length of the axis the pass transforms.  Every variant computes the
+ * same result to rounding.  PS_F32_SPLIT plans keep the radix-16-based plan
+ * (no variant 1 of passes 0, 1, 3, 4, no z variant 2); for them "pass" 5 sets the
  * number of split-bf16 product terms per DFT-16: 6 (three pieces per
  * operand, all piece products of order <= 2; the default) or 3 (two pieces,
  * order <= 1). */
@@ -205,10 +239,19 @@ const char *ps_status_str(ps_status s);
 /* Detail of the last failing call on this thread ("" if none). */
 const char *ps_last_error(void);
 
+/* Measurement aid, not a step of the method: a plain device copy of `bytes`
+ * from d_src to d_dst on `stream` (16-byte items, one per thread, in
+ * 256-thread workgroups).  Its rate is the achievable HBM bandwidth against
+ * which the pass kernels are read.  d_src, d_dst and bytes must be multiples
+ * of 16 and the arrays must not overlap (PS_ERR_INVALID). */
+ps_status ps_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *stream);
+
 /* Test hook: run a single pass of the pruned pipeline of a built plan on
  * caller arrays (in != out), in the layouts the pipeline uses between passes
  * (H = n + 1, P = 2n, HP = H rounded up to a multiple of 16; complex =
- * interleaved re, im of the plan's type):
+ * interleaved re, im of the plan's type; for a box read n^3 as nz ny nx,
+ * H as nx + 1, the y extent of T1 and T4 as ny, the ky extent of T2 and T3
+ * as 2 ny, and the z extent as nz):
  *   pass 0  x R2C   in rho[z][y][x] (n^3 real)  -> out T1[kx][z][y]  (H n n complex)
  *   pass 1  y fwd   in T1                       -> out T2[kx][ky][z] (H P n complex)
  *   pass 2  z conv  in T2 -> forward z FFT, product with the kernel, inverse, crop

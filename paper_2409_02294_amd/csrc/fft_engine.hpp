@@ -17,9 +17,12 @@
 // half of the last-stage outputs are skipped.
 //
 // Between stages the pencils live in LDS, pencil p at row p with pitch LP and
-// one pad slot every 16 elements (k -> k + k/16), which keeps both the
-// stride-1 and the stride-R access patterns of the Stockham exchange free of
-// systematic bank conflicts.
+// one pad slot every G elements (k -> k + k/G), G = 32 when the first radix
+// is 32 and 16 otherwise.  The first stage's stores run over butterflies j
+// at stride R (element j R + r), which the pad turns into an odd stride of
+// R + 1 slots for R = G, so the 8-byte stores of a wavefront spread over all
+// banks; every later stage reads and writes consecutive elements across
+// lanes, which the pad does not disturb.
 //
 // Butterfly-to-thread mapping per stage: MAP_PF puts the pencil index in the
 // fastest-varying position (lane-contiguous across pencils: coalesced access
@@ -174,9 +177,17 @@ template <int MT, int DIR> __device__ __forceinline__ void dft16_split(float2* v
     for (int q = 0; q < 8; ++q) v[q] = float2{acc[q], DIR < 0 ? acc[8 + q] : -acc[8 + q]};
 }
 
+// LDS row pitch (complex elements) of a length-P pencil with one pad slot
+// every G elements.
+constexpr int pad_pitch(int P, int G) { return P + P / G + 1; }
+constexpr int pad_shift(int r0) { return r0 == 32 ? 5 : 4; }
+
 // MT: 0 = every stage on the vector ALUs; 3 or 6 = radix-16 stages on the
 // matrix cores with that many split product terms (T = float only).
-template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> struct Engine {
+// PITCH: LDS row pitch of a pencil, when it must exceed the plan's own (two
+// plans sharing one buffer under wavefront-level synchronisation need equal
+// rows, so that each wavefront's pencils occupy the same LDS in both).
+template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0, int PITCH = 0> struct Engine {
     using V = cx<T>;
     using SA = SplitA<MT>;
     static_assert(MT == 0 || std::is_same<T, float>::value, "split matrix-core DFTs are single precision");
@@ -199,7 +210,10 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
     }
     static constexpr int P = RP::P;
     static constexpr int S = RP::S;
-    static constexpr int LP = P + P / 16 + 1;
+    static constexpr int GS = pad_shift(RP::r[0]);  // log2 of the pad granularity G
+    static constexpr int G = 1 << GS;
+    static_assert(PITCH == 0 || PITCH >= pad_pitch(P, G), "row pitch below the padded pencil");
+    static constexpr int LP = PITCH > 0 ? PITCH : pad_pitch(P, G);
     static constexpr int LDS_ELEMS = B * LP;
 
     // Twiddle source: the row and column layouts of the plan's table.  A
@@ -227,7 +241,7 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
 
     template <int s> using Regs = RegBlock<V, NB<s>, RS<s>>;
 
-    __device__ __forceinline__ static int lidx(int p, int k) { return p * LP + k + (k >> 4); }
+    __device__ __forceinline__ static int lidx(int p, int k) { return p * LP + k + (k >> GS); }
 
     // virtual thread index and element offset of this thread for stage s
     template <int s> __device__ __forceinline__ static int vthread()
@@ -312,15 +326,15 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
             pj<s, MAP>(b, p, j);
             const int k0 = (j / NSs) * NSs * Rs + (j % NSs);
             // LDS addresses as one base plus compile-time offsets where the
-            // pad-every-16 layout allows it
-            if constexpr (NSs % 16 == 0) {
-                V* base = lds + lidx(p, k0) + (ro * NSs) * 17 / 16;
+            // pad-every-G layout allows it
+            if constexpr (NSs % G == 0) {
+                V* base = lds + lidx(p, k0) + (ro * NSs) * (G + 1) / G;
 #pragma unroll
-                for (int q = 0; q < RS<s>; ++q) base[(q * NSs) * 17 / 16] = g.v[i][q];
-            } else if constexpr (NSs == 1 && Rs % 16 == 0) {
-                V* base = lds + lidx(p, k0) + ro;  // k0 = j R is a multiple of 16, ro + q < 16 or ro = 0
+                for (int q = 0; q < RS<s>; ++q) base[(q * NSs) * (G + 1) / G] = g.v[i][q];
+            } else if constexpr (NSs == 1 && Rs % G == 0) {
+                V* base = lds + lidx(p, k0) + ro;  // k0 = j R is a multiple of G, ro + q < G or ro = 0
 #pragma unroll
-                for (int q = 0; q < RS<s>; ++q) base[q + (q >> 4)] = g.v[i][q];
+                for (int q = 0; q < RS<s>; ++q) base[q + (q >> GS)] = g.v[i][q];
             } else {
 #pragma unroll
                 for (int q = 0; q < RS<s>; ++q) lds[lidx(p, k0 + (ro + q) * NSs)] = g.v[i][q];
@@ -341,10 +355,10 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0> s
             }
             int p, j;
             pj<s, MAP>(b, p, j);
-            if constexpr (Q<s> % 16 == 0) {
-                const V* base = lds + lidx(p, j) + (ro * Q<s>) * 17 / 16;
+            if constexpr (Q<s> % G == 0) {
+                const V* base = lds + lidx(p, j) + (ro * Q<s>) * (G + 1) / G;
 #pragma unroll
-                for (int q = 0; q < RS<s>; ++q) g.v[i][q] = base[(q * Q<s>) * 17 / 16];
+                for (int q = 0; q < RS<s>; ++q) g.v[i][q] = base[(q * Q<s>) * (G + 1) / G];
             } else {
 #pragma unroll
                 for (int q = 0; q < RS<s>; ++q) g.v[i][q] = lds[lidx(p, j + (ro + q) * Q<s>)];

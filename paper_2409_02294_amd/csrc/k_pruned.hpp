@@ -43,6 +43,17 @@ __host__ __device__ constexpr int t4_pitch(int H) { return (H + 15) / 16 * 16; }
 // coordinates, using a caller-provided LDS buffer of at least LDS elements),
 // wrapped below as a one-tile-per-workgroup kernel; the y and z passes also
 // have persistent kernels that walk the tiles with a one-tile prefetch.
+//
+// Boxes.  A pass transforms one axis, whose length is the template P; with
+// BOX the extents of the other two axes come from the solve record (nx, ny,
+// nz cells; H = n + 1 and padded lengths 2n per axis), so one kernel per
+// axis length serves every box shape.  Without BOX all three axes have
+// length P / 2 at compile time.
+template <bool BOX> __device__ __forceinline__ int ext(int box_value, int cubic_value)
+{
+    if constexpr (BOX) return box_value;
+    else return cubic_value;
+}
 
 // Element-wise copy of COUNT items src(e) -> dst(e, v) by the NT threads of a
 // workgroup, each thread issuing all its loads before its stores, so a tile
@@ -67,27 +78,29 @@ __device__ __forceinline__ void block_copy(SRC&& src, DST&& dst)
 // ---------------------------------------------------------------------------
 // x_r2c: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXR2C {
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false> struct TileXR2C {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Fwd, 8, NT, false, MT>;
-    static constexpr int N = P / 2, H = N + 1;
+    static constexpr int N = P / 2, H = N + 1;  // x length, half spectrum
     static constexpr int LDS = E::LDS_ELEMS;
     __device__ __forceinline__ static void run(int bx, int by, const T* __restrict__ rho, V* __restrict__ t1,
-                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa,
+                                               int ny_box = 0, int nz_box = 0)
     {
+        const int Ny = ext<BOX>(ny_box, N), Nz = ext<BOX>(nz_box, N);
         const int y0 = bx * 16;
         const int z = by;
-        const T* plane = rho + ((size_t)z * N + y0) * N;  // block-uniform base, 32-bit offsets below
+        const T* plane = rho + ((size_t)z * Ny + y0) * N;  // block-uniform base, 32-bit offsets below
         auto ld = [&](int p, int idx) -> V {
             const int ya = y0 + 2 * p;
-            const T a = ya < N ? plane[(unsigned)(2 * p * N + idx)] : T(0);
-            const T b = ya + 1 < N ? plane[(unsigned)((2 * p + 1) * N + idx)] : T(0);
+            const T a = ya < Ny ? plane[(unsigned)(2 * p * N + idx)] : T(0);
+            const T b = ya + 1 < Ny ? plane[(unsigned)((2 * p + 1) * N + idx)] : T(0);
             return V{a, b};
         };
         auto st = [&](int p, int idx, V v) { lds[E::lidx(p, idx)] = v; };
         E::template run<-1, MAP_EF, MAP_MID, MAP_EF, N, P, true>(lds, tw, ld, st, sa);
         __syncthreads();
-        V* t1z = t1 + (size_t)z * N;
+        V* t1z = t1 + (size_t)z * Ny;
         // separate the two half spectra of each packed pair: element e is
         // (row e % 16, k = e / 16), written to T1[k][z][y0 + row]
         auto sep = [&](int e) -> V {
@@ -100,7 +113,7 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXR
         };
         auto put = [&](int e, V x) {
             const int row = e & 15, k = e >> 4;
-            if (y0 + row < N) t1z[(unsigned)(k * N * N + y0 + row)] = x;
+            if (y0 + row < Ny) t1z[(unsigned)(k * Nz * Ny + y0 + row)] = x;
         };
         block_copy<V, NT, 16 * H>(sep, put);
     }
@@ -109,23 +122,25 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXR
 // ---------------------------------------------------------------------------
 // y_fwd: ZT z-pencils of one kx; tile (z-tile bx, kx by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struct TileYFwd {
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false> struct TileYFwd {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ZT, NT, false, MT>;
-    static constexpr int N = P / 2;
+    static constexpr int N = P / 2;  // y length
     static constexpr int LDS = E::LDS_ELEMS;
     __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t1, V* __restrict__ t2,
-                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa,
+                                               int nz_box = 0)
     {
+        const int Nz = ext<BOX>(nz_box, N);
         const int z0 = bx * ZT;
         const int kx = by;
-        const V* in = t1 + ((size_t)kx * N + z0) * N;
-        V* out = t2 + (size_t)kx * P * N + z0;
+        const V* in = t1 + ((size_t)kx * Nz + z0) * N;
+        V* out = t2 + (size_t)kx * P * Nz + z0;
         auto ld = [&](int p, int idx) -> V {
-            return z0 + p < N ? in[(unsigned)(p * N + idx)] : V{T(0), T(0)};
+            return z0 + p < Nz ? in[(unsigned)(p * N + idx)] : V{T(0), T(0)};
         };
         auto st = [&](int p, int idx, V v) {
-            if (z0 + p < N) out[(unsigned)(idx * N + p)] = v;
+            if (z0 + p < Nz) out[(unsigned)(idx * Nz + p)] = v;
         };
         E::template run<-1, MAP_EF, MAP_MID, MAP_PF, N, P>(lds, tw, ld, st, sa);
     }
@@ -137,36 +152,43 @@ template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struc
 // and those stage exchanges synchronise the wavefront only; the last stage
 // spans the workgroup so its stores form rows of B interleaved pencils.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT> struct TileZConv {
+template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT, bool BOX = false> struct TileZConv {
     using V = cx<T>;
-    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE, MT>;
-    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE, MT>;
-    static_assert(EF::LDS_ELEMS == EI::LDS_ELEMS, "plans share one LDS buffer");
-    static constexpr int N = P / 2, H = N + 1;
+    // the two plans share one LDS buffer with one row pitch (their pad
+    // granularities may differ), so a wavefront's pencils sit in the same rows
+    static constexpr int LPF = pad_pitch(P, 1 << pad_shift(PlanFor<P, FAM>::Fwd::r[0]));
+    static constexpr int LPI = pad_pitch(P, 1 << pad_shift(PlanFor<P, FAM>::Inv::r[0]));
+    static constexpr int LPZ = LPF > LPI ? LPF : LPI;
+    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE, MT, LPZ>;
+    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE, MT, LPZ>;
+    static constexpr int N = P / 2, H = N + 1;  // z length, z half spectrum
     static constexpr int LDS = EF::LDS_ELEMS;
+    static_assert(EF::LDS_ELEMS == EI::LDS_ELEMS, "plans share one LDS buffer");
     __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t2, V* __restrict__ t3,
                                                const T* __restrict__ ghat, const V* __restrict__ twf,
-                                               const V* __restrict__ twi, V* lds, const typename EF::SA& sa)
+                                               const V* __restrict__ twi, V* lds, const typename EF::SA& sa,
+                                               int ny_box = 0)
     {
         constexpr int MAP_IO = WAVE ? MAP_WV : MAP_EF;
         constexpr int SL = EF::S - 1;
+        const int Ny = ext<BOX>(ny_box, N), Py = 2 * Ny, Hy = Ny + 1;
         const int ky0 = bx * B;
         const int kx = by;
-        const V* in = t2 + ((size_t)kx * P + ky0) * N;  // pencil p at in + p N
-        V* out = t3 + (size_t)kx * N * P + ky0;         // element (z, p) at out[z P + p]
-        const T* grow = ghat + (size_t)kx * H * H;
+        const V* in = t2 + ((size_t)kx * Py + ky0) * N;  // pencil p at in + p N
+        V* out = t3 + (size_t)kx * N * Py + ky0;         // element (z, p) at out[z Py + p]
+        const T* grow = ghat + (size_t)kx * Hy * H;
         auto ld = [&](int p, int idx) -> V { return in[(unsigned)(p * N + idx)]; };
         typename EF::template Regs<SL> g;
         EF::template run_to_regs<-1, MAP_IO, MAP_IO, MAP_IO, N>(lds, twf, ld, g, sa);
         // multiply by the real, even transformed kernel at (kz, ky, kx)
         auto mul = [&](int p, int kz, V& v) {
             const int ky = ky0 + p;
-            const T* gr = grow + (unsigned)((ky <= N ? ky : P - ky) * H);
+            const T* gr = grow + (unsigned)((ky <= Ny ? ky : Py - ky) * H);
             const T gv = gr[kz <= N ? kz : P - kz];
             v = V{v.x * gv, v.y * gv};
         };
         EF::template for_each_out<SL, MAP_IO>(g, mul);
-        auto st = [&](int p, int idx, V v) { out[(unsigned)(idx * P + p)] = v; };
+        auto st = [&](int p, int idx, V v) { out[(unsigned)(idx * Py + p)] = v; };
         EI::template run_from_regs<+1, MAP_IO, MAP_IO, MAP_PF, N>(lds, twi, g, st, sa);
     }
 };
@@ -174,23 +196,25 @@ template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT> struct T
 // ---------------------------------------------------------------------------
 // y_inv: ZT consecutive kx pencils of one z; tile (kx-tile bx, z by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struct TileYInv {
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false> struct TileYInv {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT, false, MT>;
-    static constexpr int N = P / 2, H = N + 1, HP = t4_pitch(H);
+    static constexpr int N = P / 2;  // y length
     static constexpr int LDS = E::LDS_ELEMS;
     __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t3, V* __restrict__ t4,
-                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa,
+                                               int nx_box = 0, int nz_box = 0)
     {
+        const int Nz = ext<BOX>(nz_box, N), Hx = ext<BOX>(nx_box, N) + 1, HP = t4_pitch(Hx);
         const int kx0 = bx * ZT;
         const int z = by;
-        const V* in = t3 + ((size_t)kx0 * N + z) * P;  // pencil p (kx0 + p) at in + p N P
-        V* out = t4 + (size_t)z * N * HP + kx0;        // element (y, p) at out[y HP + p]
+        const V* in = t3 + ((size_t)kx0 * Nz + z) * P;  // pencil p (kx0 + p) at in + p Nz P
+        V* out = t4 + (size_t)z * N * HP + kx0;         // element (y, p) at out[y HP + p]
         auto ld = [&](int p, int idx) -> V {
-            return kx0 + p < H ? in[(unsigned)(p * N * P + idx)] : V{T(0), T(0)};
+            return kx0 + p < Hx ? in[(unsigned)(p * Nz * P + idx)] : V{T(0), T(0)};
         };
         auto st = [&](int p, int idx, V v) {
-            if (kx0 + p < H) out[(unsigned)(idx * HP + p)] = v;
+            if (kx0 + p < Hx) out[(unsigned)(idx * HP + p)] = v;
         };
         E::template run<+1, MAP_EF, MAP_MID, MAP_PF, P, N>(lds, tw, ld, st, sa);
     }
@@ -199,22 +223,24 @@ template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT> struc
 // ---------------------------------------------------------------------------
 // x_c2r: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXC2R {
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false> struct TileXC2R {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT, false, MT>;
-    static constexpr int N = P / 2, H = N + 1, HP = t4_pitch(H);
+    static constexpr int N = P / 2, H = N + 1, HP = t4_pitch(H);  // x length, half spectrum, T4 pitch
     static constexpr int XP = H + 1;  // pitch of the staged half spectra
     static constexpr int LDS = E::LDS_ELEMS > 16 * XP ? E::LDS_ELEMS : 16 * XP;
     __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t4, T* __restrict__ phi,
-                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa)
+                                               const V* __restrict__ tw, V* lds, const typename E::SA& sa,
+                                               int ny_box = 0)
     {
+        const int Ny = ext<BOX>(ny_box, N);
         const int y0 = bx * 16;
         const int z = by;
-        const V* rows = t4 + ((size_t)z * N + y0) * HP;  // 16 consecutive rows of H (pitch HP)
+        const V* rows = t4 + ((size_t)z * Ny + y0) * HP;  // 16 consecutive rows of H (pitch HP)
         block_copy<V, NT, 16 * H>(
             [&](int e) -> V {
                 const int row = e / H, k = e - row * H;
-                return y0 + row < N ? rows[(unsigned)(row * HP + k)] : V{T(0), T(0)};
+                return y0 + row < Ny ? rows[(unsigned)(row * HP + k)] : V{T(0), T(0)};
             },
             [&](int e, V v) {
                 const int row = e / H, k = e - row * H;
@@ -238,11 +264,11 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT> struct TileXC
             }
             return V{a.x - b.y, a.y + b.x};
         };
-        T* plane = phi + ((size_t)z * N + y0) * N;
+        T* plane = phi + ((size_t)z * Ny + y0) * N;
         auto st = [&](int p, int idx, V v) {
             const int ya = y0 + 2 * p;
-            if (ya < N) plane[(unsigned)(2 * p * N + idx)] = v.x;
-            if (ya + 1 < N) plane[(unsigned)((2 * p + 1) * N + idx)] = v.y;
+            if (ya < Ny) plane[(unsigned)(2 * p * N + idx)] = v.x;
+            if (ya + 1 < Ny) plane[(unsigned)((2 * p + 1) * N + idx)] = v.y;
         };
         E::template run<+1, MAP_EF, MAP_MID, MAP_EF, P, N>(lds, tw, ld, st, sa);
     }
@@ -261,41 +287,42 @@ template <typename X> __device__ __forceinline__ X* gp(PS_GLOBAL void* p)
 {
     return (X*)(PS_GLOBAL X*)p;
 }
-template <typename V, int FAM> __device__ __forceinline__ const V* tw_fwd(const SolveRec& s)
+// twiddle tables of axis AX (0 x, 1 y, 2 z) for plan family FAM
+template <typename V, int FAM, int AX> __device__ __forceinline__ const V* tw_fwd(const SolveRec& s)
 {
-    return gp<const V>(FAM == 1 ? s.twf1 : s.twf);
+    return gp<const V>(FAM == 1 ? s.twf1[AX] : s.twf[AX]);
 }
-template <typename V, int FAM> __device__ __forceinline__ const V* tw_inv(const SolveRec& s)
+template <typename V, int FAM, int AX> __device__ __forceinline__ const V* tw_inv(const SolveRec& s)
 {
-    return gp<const V>(FAM == 1 ? s.twi1 : s.twi);
+    return gp<const V>(FAM == 1 ? s.twi1[AX] : s.twi[AX]);
 }
 
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false>
 __global__ __launch_bounds__(NT) void k_x_r2c(const T* in, cx<T>* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileXR2C<T, P, FAM, NT, MAP_MID, MT>;
+    using TL = TileXR2C<T, P, FAM, NT, MAP_MID, MT, BOX>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
     const SolveRec& s = list[blockIdx.z];
-    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const T>(s.rho), out ? out : gp<V>(s.t1), tw_fwd<V, FAM>(s), lds,
-            sa);
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const T>(s.rho), out ? out : gp<V>(s.t1), tw_fwd<V, FAM, 0>(s),
+            lds, sa, ext<BOX>(s.ny, 0), ext<BOX>(s.nz, 0));
 }
 
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileYFwd<T, P, FAM, ZT, NT, MAP_MID, MT>;
+    using TL = TileYFwd<T, P, FAM, ZT, NT, MAP_MID, MT, BOX>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
     const SolveRec& s = list[blockIdx.z];
-    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t1), out ? out : gp<V>(s.t2), tw_fwd<V, FAM>(s), lds,
-            sa);
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t1), out ? out : gp<V>(s.t2), tw_fwd<V, FAM, 1>(s),
+            lds, sa, ext<BOX>(s.nz, 0));
 }
 
 // z-pass tile order.  Pencils ky and P - ky multiply by the same Ghat rows,
@@ -315,18 +342,20 @@ template <int NTILE> __device__ __forceinline__ int z_tile(int l)
     }
 }
 
-template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT>
+// (a box's tiles run in launch order: its ky extent is not known at compile time)
+template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT, bool BOX = false>
 __global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
                                                const unsigned short* __restrict__ stab)
 {
-    using TL = TileZConv<T, P, FAM, B, NT, WAVE, MT>;
+    using TL = TileZConv<T, P, FAM, B, NT, WAVE, MT, BOX>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::EF::SA sa;
     sa.load(stab);
     const SolveRec& s = list[blockIdx.z];
-    TL::run(z_tile<P / B>(blockIdx.x), blockIdx.y, in ? in : gp<const V>(s.t2), out ? out : gp<V>(s.t3),
-            gp<const T>(s.ghat), tw_fwd<V, FAM>(s), tw_inv<V, FAM>(s), lds, sa);
+    const int bx = BOX ? (int)blockIdx.x : z_tile<P / B>(blockIdx.x);
+    TL::run(bx, blockIdx.y, in ? in : gp<const V>(s.t2), out ? out : gp<V>(s.t3), gp<const T>(s.ghat),
+            tw_fwd<V, FAM, 2>(s), tw_inv<V, FAM, 2>(s), lds, sa, ext<BOX>(s.ny, 0));
 }
 
 // Persistent y passes with a one-tile prefetch: workgroups walk the tiles
@@ -356,7 +385,7 @@ __global__ __launch_bounds__(NT) void k_y_fwd_pf(const cx<T>* in, cx<T>* out, co
     const int total = NZ * H * count;
     int t = blockIdx.x;
     if (t >= total) return;
-    copy_columns<V, RP, NT>(tw_fwd<V, FAM>(list[0]), lcol);  // made visible by the first stage's barrier
+    copy_columns<V, RP, NT>(tw_fwd<V, FAM, 1>(list[0]), lcol);  // made visible by the first stage's barrier
     auto tile = [&](int u, int& zs, int& kx, int& z0) {
         zs = u / (NZ * H);
         const int r = u - zs * (NZ * H);
@@ -382,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_y_fwd_pf(const cx<T>* in, cx<T>* out, co
         auto st = [&](int p, int idx, V v) {
             if (z0 + p < N) pout[(unsigned)(idx * N + p)] = v;
         };
-        E::template run_from_regs<-1, MAP_EF, MAP_EF, MAP_PF, P>(lds, typename E::TW(tw_fwd<V, FAM>(s), lcol), cur,
+        E::template run_from_regs<-1, MAP_EF, MAP_EF, MAP_PF, P>(lds, typename E::TW(tw_fwd<V, FAM, 1>(s), lcol), cur,
                                                                   st, sa);
         cur = nxt;
     }
@@ -404,7 +433,7 @@ __global__ __launch_bounds__(NT) void k_y_inv_pf(const cx<T>* in, cx<T>* out, co
     const int total = NK * N * count;
     int t = blockIdx.x;
     if (t >= total) return;
-    copy_columns<V, RP, NT>(tw_inv<V, FAM>(list[0]), lcol);  // made visible by the first stage's barrier
+    copy_columns<V, RP, NT>(tw_inv<V, FAM, 1>(list[0]), lcol);  // made visible by the first stage's barrier
     // z fastest: consecutive tiles read neighbouring rows of the same 16 kx planes
     auto tile = [&](int u, int& zs, int& kx0, int& z) {
         zs = u / (NK * N);
@@ -433,7 +462,7 @@ __global__ __launch_bounds__(NT) void k_y_inv_pf(const cx<T>* in, cx<T>* out, co
         auto st = [&](int p, int idx, V v) {
             if (kx0 + p < H) pout[(unsigned)(idx * HP + p)] = v;
         };
-        E::template run_from_regs<+1, MAP_EF, MAP_EF, MAP_PF, N>(lds, typename E::TW(tw_inv<V, FAM>(s), lcol), cur,
+        E::template run_from_regs<+1, MAP_EF, MAP_EF, MAP_PF, N>(lds, typename E::TW(tw_inv<V, FAM, 1>(s), lcol), cur,
                                                                   st, sa);
         cur = nxt;
     }
@@ -472,10 +501,10 @@ __global__ __launch_bounds__(NT) void k_z_conv_pf(const cx<T>* in, cx<T>* out, c
     if (t >= total) return;
     {
         // columns follow the rows in each table; one plan serves every record of a launch
-        const V* cf = tw_fwd<V, FAM>(list[0]) + CF;
+        const V* cf = tw_fwd<V, FAM, 2>(list[0]) + CF;
         for (int e = threadIdx.x; e < CF; e += NT) lcol[e] = cf[e];
         if constexpr (!SAME) {
-            const V* ci = tw_inv<V, FAM>(list[0]) + RI::tw_size();
+            const V* ci = tw_inv<V, FAM, 2>(list[0]) + RI::tw_size();
             for (int e = threadIdx.x; e < CI; e += NT) lcol[CF + e] = ci[e];
         }
         __syncthreads();
@@ -510,43 +539,43 @@ __global__ __launch_bounds__(NT) void k_z_conv_pf(const cx<T>* in, cx<T>* out, c
         if (t + (int)gridDim.x < total) load(t + gridDim.x, nxt);
         typename EF::template Regs<SL> g;
         EF::template run_to_regs_loaded<-1, MAP_WV, MAP_WV, MAP_WV>(
-            lds, typename EF::TW(tw_fwd<V, FAM>(s), lcol), cur, g, sa);
+            lds, typename EF::TW(tw_fwd<V, FAM, 2>(s), lcol), cur, g, sa);
         EF::template scale<SL>(g, gv);
         V* pout = (out ? out : gp<V>(s.t3)) + (size_t)kx * N * P + ky0;
         auto st = [&](int p, int idx, V v) { pout[(unsigned)(idx * P + p)] = v; };
         EI::template run_from_regs<+1, MAP_WV, MAP_WV, MAP_PF, N>(
-            lds, typename EI::TW(tw_inv<V, FAM>(s), SAME ? lcol : lcol + CF), g, st, sa);
+            lds, typename EI::TW(tw_inv<V, FAM, 2>(s), SAME ? lcol : lcol + CF), g, st, sa);
         __syncthreads();  // the last stage read every pencil's rows; the next tile rewrites them
         cur = nxt;
     }
 }
 
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT>
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false>
 __global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileYInv<T, P, FAM, ZT, NT, MAP_MID, MT>;
+    using TL = TileYInv<T, P, FAM, ZT, NT, MAP_MID, MT, BOX>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
     const SolveRec& s = list[blockIdx.z];
-    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t3), out ? out : gp<V>(s.t1), tw_inv<V, FAM>(s), lds,
-            sa);
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t3), out ? out : gp<V>(s.t1), tw_inv<V, FAM, 1>(s),
+            lds, sa, ext<BOX>(s.nx, 0), ext<BOX>(s.nz, 0));
 }
 
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT>
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* in, T* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileXC2R<T, P, FAM, NT, MAP_MID, MT>;
+    using TL = TileXC2R<T, P, FAM, NT, MAP_MID, MT, BOX>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
     sa.load(stab);
     const SolveRec& s = list[blockIdx.z];
-    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t1), out ? out : gp<T>(s.phi), tw_inv<V, FAM>(s), lds,
-            sa);
+    TL::run(blockIdx.x, blockIdx.y, in ? in : gp<const V>(s.t1), out ? out : gp<T>(s.phi), tw_inv<V, FAM, 0>(s),
+            lds, sa, ext<BOX>(s.ny, 0));
 }
 
 }  // namespace ps

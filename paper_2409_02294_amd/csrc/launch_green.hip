@@ -6,46 +6,65 @@
 
 namespace ps {
 
-template <int P> static hipError_t green_passes(const GreenBufs& b)
+template <int P> static void green_x(const GreenBufs& b)
 {
-    constexpr int N = P / 2, H = N + 1;
     constexpr int NT = threads_for(8, P);
-    const double2* tw = static_cast<const double2*>(b.twf64);
-    const dim3 grid((H + 15) / 16, H);
-    hipLaunchKernelGGL((k_green_x<P, NT, MAP_EF>), grid, dim3(NT), 0, b.stream, b.g1, tw, b.dx, b.sy, b.sz,
-                       b.self_value);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_green_y<P, NT, MAP_EF>), grid, dim3(NT), 0, b.stream, b.g1, tw);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int hy = b.ny + 1, hz = b.nz + 1;
+    hipLaunchKernelGGL((k_green_x<P, NT, MAP_EF>), dim3((hy + 15) / 16, hz), dim3(NT), 0, b.stream, b.g1,
+                       static_cast<const double2*>(b.twf64[0]), hy, hz, b.dx, b.sy, b.sz, b.self_value);
+}
+
+template <int P> static void green_y(const GreenBufs& b)
+{
+    constexpr int NT = threads_for(8, P);
+    const int hx = b.nx + 1, hz = b.nz + 1;
+    hipLaunchKernelGGL((k_green_y<P, NT, MAP_EF>), dim3((hz + 15) / 16, hx), dim3(NT), 0, b.stream, b.g1,
+                       static_cast<const double2*>(b.twf64[1]), hz);
+}
+
+template <int P> static void green_z(const GreenBufs& b)
+{
+    constexpr int NT = threads_for(8, P);
+    const int hx = b.nx + 1, hy = b.ny + 1;
+    const dim3 grid((hy + 15) / 16, hx);
+    const double2* tw = static_cast<const double2*>(b.twf64[2]);
     if (b.out_f32) {
         if (b.plain_layout)
             hipLaunchKernelGGL((k_green_z<float, P, NT, MAP_EF, true>), grid, dim3(NT), 0, b.stream, b.g1,
-                               static_cast<float*>(b.ghat), tw, b.scale);
+                               static_cast<float*>(b.ghat), tw, hx, hy, b.scale);
         else
             hipLaunchKernelGGL((k_green_z<float, P, NT, MAP_EF, false>), grid, dim3(NT), 0, b.stream, b.g1,
-                               static_cast<float*>(b.ghat), tw, b.scale);
+                               static_cast<float*>(b.ghat), tw, hx, hy, b.scale);
     } else {
         if (b.plain_layout)
             hipLaunchKernelGGL((k_green_z<double, P, NT, MAP_EF, true>), grid, dim3(NT), 0, b.stream, b.g1,
-                               static_cast<double*>(b.ghat), tw, b.scale);
+                               static_cast<double*>(b.ghat), tw, hx, hy, b.scale);
         else
             hipLaunchKernelGGL((k_green_z<double, P, NT, MAP_EF, false>), grid, dim3(NT), 0, b.stream, b.g1,
-                               static_cast<double*>(b.ghat), tw, b.scale);
+                               static_cast<double*>(b.ghat), tw, hx, hy, b.scale);
     }
-    return hipGetLastError();
 }
 
-hipError_t green_run(int P, const GreenBufs& b)
+// The three passes, each on its axis's padded length.
+hipError_t green_run(const GreenBufs& b)
 {
-    switch (P) {
-#define PS_CASE(PP) \
-    case PP: return green_passes<PP>(b);
-        PS_FOR_EACH_P(PS_CASE)
+    for (int axis = 0; axis < 3; ++axis) {
+        const int P = 2 * (axis == 0 ? b.nx : axis == 1 ? b.ny : b.nz);
+        switch (P) {
+#define PS_CASE(PP)                      \
+    case PP:                             \
+        if (axis == 0) green_x<PP>(b);   \
+        else if (axis == 1) green_y<PP>(b); \
+        else green_z<PP>(b);             \
+        break;
+            PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
-    default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 template <class RP> static void rlist(std::vector<int>& v) { v.assign(RP::r, RP::r + RP::S); }

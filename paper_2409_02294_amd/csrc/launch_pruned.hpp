@@ -107,7 +107,81 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
         hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N, b.count), dim3(NTX), 0,
                            b.stream, static_cast<const V*>(b.in[4]), static_cast<T*>(b.out[4]), b.list, b.stab);
     }
+
+    // Box forms: P is the transformed axis's length; the grids cover the
+    // other two axes' extents b.nx, b.ny, b.nz (the kernels read them from
+    // the solve records, so every record of a launch has the same box).
+    static void x_r2c_box(const PrunedBufs& b)
+    {
+        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTX, MAP_EF, MT, true>), dim3((b.ny + 15) / 16, b.nz, b.count),
+                           dim3(NTX), 0, b.stream, static_cast<const T*>(b.in[0]), static_cast<V*>(b.out[0]), b.list,
+                           b.stab);
+    }
+    static void y_fwd_box(const PrunedBufs& b)
+    {
+        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF, MT, true>),
+                           dim3((b.nz + ZT - 1) / ZT, b.nx + 1, b.count), dim3(NTY), 0, b.stream,
+                           static_cast<const V*>(b.in[1]), static_cast<V*>(b.out[1]), b.list, b.stab);
+    }
+    template <bool WAVE> static void z_conv_box(const PrunedBufs& b)
+    {
+        constexpr int NTZ = WAVE ? wave_threads(ZB, P, E) : threads_for(ZB, P, E);
+        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT, true>), dim3(2 * b.ny / ZB, b.nx + 1, b.count),
+                           dim3(NTZ), 0, b.stream, static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list,
+                           b.stab);
+    }
+    static void y_inv_box(const PrunedBufs& b)
+    {
+        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT, true>),
+                           dim3((b.nx + 1 + ZT - 1) / ZT, b.nz, b.count), dim3(NTY), 0, b.stream,
+                           static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab);
+    }
+    static void x_c2r_box(const PrunedBufs& b)
+    {
+        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF, MT, true>), dim3((b.ny + 15) / 16, b.nz, b.count),
+                           dim3(NTX), 0, b.stream, static_cast<const V*>(b.in[4]), static_cast<T*>(b.out[4]), b.list,
+                           b.stab);
+    }
 };
+
+// One pass of a box solve with P its axis's length.  Boxes run the
+// one-tile-per-workgroup kernels (persistent variants are for cubes).
+template <typename T, int P, int MT> static hipError_t box_pass(int pass, const PrunedBufs& b)
+{
+    using L0 = PassLaunch<T, P, 0, MT>;
+    constexpr bool F1 = has_fam1<P>() && MT == 0;
+    using L1 = PassLaunch<T, P, F1 ? 1 : 0, MT>;
+    const PrunedVariant& v = b.var;
+    switch (pass) {
+    case 0:
+        if (v.x_fam == 1 && F1) L1::x_r2c_box(b);
+        else L0::x_r2c_box(b);
+        break;
+    case 1:
+        if (v.y_fam & 2) return hipErrorInvalidValue;
+        if ((v.y_fam & 1) && F1) L1::y_fwd_box(b);
+        else L0::y_fwd_box(b);
+        break;
+    case 2:
+        if (v.zmode >= 3) return hipErrorInvalidValue;
+        if (v.zmode == 2 && F1) L1::template z_conv_box<true>(b);
+        else if (v.zmode >= 1) L0::template z_conv_box<true>(b);
+        else L0::template z_conv_box<false>(b);
+        break;
+    case 3:
+        if (v.yi_fam & 2) return hipErrorInvalidValue;
+        if ((v.yi_fam & 1) && F1) L1::y_inv_box(b);
+        else L0::y_inv_box(b);
+        break;
+    case 4:
+        if (v.xc_fam == 1 && F1) L1::x_c2r_box(b);
+        else L0::x_c2r_box(b);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 // Split matrix-core plans keep the radix-16 family (family 1 has no radix-16 stage).
 template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int hi, const PrunedBufs& b)
@@ -128,13 +202,13 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             break;
         case 2:
             // (a persistent form that does not fit in LDS runs as the wave-owned pass)
-            if constexpr (MT == 0 && PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1 && z_pf_fits<T, P, F1 ? 1 : 0, 32, MT>()) {
+            if constexpr (PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1 && z_pf_fits<T, P, F1 ? 1 : 0, 32, MT>()) {
                 if (v.zmode == 3) {  // persistent: radix-32 family where it exists
                     L1::template z_conv_pf<32>(b);
                     break;
                 }
             }
-            if constexpr (MT == 0 && PlanFor<P, 0>::Fwd::S > 1 && z_pf_fits<T, P, 0, 16, MT>()) {
+            if constexpr (PlanFor<P, 0>::Fwd::S > 1 && z_pf_fits<T, P, 0, 16, MT>()) {
                 if (v.zmode == 4) {  // persistent: radix-16 family, one 1024-point pencil per wavefront
                     L0::template z_conv_pf<16>(b);
                     break;
@@ -161,15 +235,32 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
     return hipSuccess;
 }
 
-template <typename T, int MT> static hipError_t pruned_dispatch(int P, int lo, int hi, const PrunedBufs& b)
+// Passes [lo, hi): a cube's run on its one length; a box's each on the
+// length of the axis it transforms (x: passes 0 and 4, y: 1 and 3, z: 2).
+template <typename T, int MT> static hipError_t pruned_dispatch(int lo, int hi, const PrunedBufs& b)
 {
-    switch (P) {
+    if (!b.box) {
+        switch (b.px) {
 #define PS_CASE(PP) \
     case PP: return pruned_passes<T, PP, MT>(lo, hi, b);
-        PS_FOR_EACH_P(PS_CASE)
+            PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
-    default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
     }
+    for (int pass = lo; pass < hi; ++pass) {
+        const int P = pass == 2 ? b.pz : (pass == 1 || pass == 3) ? b.py : b.px;
+        hipError_t e = hipErrorInvalidValue;
+        switch (P) {
+#define PS_CASE(PP) \
+    case PP: e = box_pass<T, PP, MT>(pass, b); break;
+            PS_FOR_EACH_P(PS_CASE)
+#undef PS_CASE
+        default: break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace ps

@@ -2,6 +2,6 @@
 // cores (split operands, 6 or 3 product terms).
 #include "launch_pruned.hpp"
 namespace ps {
-hipError_t pruned_run_split6(int P, int lo, int hi, const PrunedBufs& b) { return pruned_dispatch<float, 6>(P, lo, hi, b); }
-hipError_t pruned_run_split3(int P, int lo, int hi, const PrunedBufs& b) { return pruned_dispatch<float, 3>(P, lo, hi, b); }
+hipError_t pruned_run_split6(int lo, int hi, const PrunedBufs& b) { return pruned_dispatch<float, 6>(lo, hi, b); }
+hipError_t pruned_run_split3(int lo, int hi, const PrunedBufs& b) { return pruned_dispatch<float, 3>(lo, hi, b); }
 }  // namespace ps

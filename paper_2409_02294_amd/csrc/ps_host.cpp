@@ -214,16 +214,19 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb)
 }  // namespace
 
 struct ps_plan_s {
-    int n = 0, P = 0, H = 0;
+    int n = 0, P = 0, H = 0;              // x axis (every axis of a cube)
+    int nx = 0, ny = 0, nz = 0;           // cells per axis
+    bool box = false;                     // axes of unequal length: the kernels built for boxes
     double dx = 0.0, dy = 0.0, dz = 0.0;  // cell spacings along x, y, z
     ps_precision prec = PS_F64;
     size_t real_bytes = 0;
-    std::vector<int> radices;
+    std::vector<int> radices;             // forward radix plan of the x axis
     // workspace layout (byte offsets)
     std::vector<unsigned char> tables;
     size_t off_tab = 0, tab_bytes = 0;
-    size_t tw_f = 0, tw_i = 0, tw_f64 = 0;  // offsets inside the table blob
-    size_t tw_f1 = 0, tw_i1 = 0;            // family-1 plan tables
+    // offsets inside the table blob, per axis (x, y, z; equal axes share tables)
+    size_t tw_f[3] = {}, tw_i[3] = {}, tw_f64[3] = {};
+    size_t tw_f1[3] = {}, tw_i1[3] = {};  // family-1 plan tables
     size_t split_tab = 0;                   // split-bf16 DFT-16 matrix pieces
     ps::PrunedVariant var;                  // kernel variant per pass
     size_t off_ghat = 0, ghat_bytes = 0;
@@ -266,19 +269,27 @@ ps_status check_plan(ps_plan p)
     return PS_OK;
 }
 
+size_t cells(ps_plan p) { return (size_t)p->nx * p->ny * p->nz; }
+int axis_pad(ps_plan p, int axis) { return 2 * (axis == 0 ? p->nx : axis == 1 ? p->ny : p->nz); }
+
 ps::SolveRec solve_rec(ps_plan p, const void* rho, void* phi)
 {
-    ps::SolveRec r;
+    ps::SolveRec r{};
     r.rho = rho;
     r.phi = phi;
     r.t1 = p->ws + p->off_t1;
     r.t2 = p->ws + p->off_t2;
     r.t3 = p->ws + p->off_t3;
     r.ghat = p->ws + p->off_ghat;
-    r.twf = p->ws + p->off_tab + p->tw_f;
-    r.twi = p->ws + p->off_tab + p->tw_i;
-    r.twf1 = p->ws + p->off_tab + p->tw_f1;
-    r.twi1 = p->ws + p->off_tab + p->tw_i1;
+    for (int a = 0; a < 3; ++a) {
+        r.twf[a] = p->ws + p->off_tab + p->tw_f[a];
+        r.twi[a] = p->ws + p->off_tab + p->tw_i[a];
+        r.twf1[a] = p->ws + p->off_tab + p->tw_f1[a];
+        r.twi1[a] = p->ws + p->off_tab + p->tw_i1[a];
+    }
+    r.nx = p->nx;
+    r.ny = p->ny;
+    r.nz = p->nz;
     return r;
 }
 
@@ -294,10 +305,17 @@ ps::PrunedBufs pruned_bufs(ps_plan p, const void* rho, void* phi, hipStream_t s)
     b.stab = reinterpret_cast<const unsigned short*>(p->ws + p->off_tab + p->split_tab);
     b.var = p->var;
     b.stream = s;
+    b.px = axis_pad(p, 0);
+    b.py = axis_pad(p, 1);
+    b.pz = axis_pad(p, 2);
+    b.box = p->box;
+    b.nx = p->nx;
+    b.ny = p->ny;
+    b.nz = p->nz;
     return b;
 }
 
-hipError_t run_pruned(ps_precision prec, int P, int lo, int hi, const ps::PrunedBufs& b);
+hipError_t run_pruned(ps_precision prec, int lo, int hi, const ps::PrunedBufs& b);
 
 // The kernels of one solve, enqueued on `st` (arguments already checked).
 hipError_t enqueue_solve(ps_plan p, const void* d_rho, void* d_phi, hipStream_t st)
@@ -309,17 +327,17 @@ hipError_t enqueue_solve(ps_plan p, const void* d_rho, void* d_phi, hipStream_t 
         b.pad = p->ws + p->off_pad;
         b.spec = p->ws + p->off_spec;
         b.ghat = p->ws + p->off_ghat;
-        b.twf = p->ws + p->off_tab + p->tw_f;
-        b.twi = p->ws + p->off_tab + p->tw_i;
+        b.twf = p->ws + p->off_tab + p->tw_f[0];
+        b.twi = p->ws + p->off_tab + p->tw_i[0];
         b.stream = st;
         return is_f64(p->prec) ? ps::plain_run_f64(p->P, b) : ps::plain_run_f32(p->P, b);
     }
     const ps::PrunedBufs b = pruned_bufs(p, d_rho, d_phi, st);
-    return run_pruned(p->prec, p->P, 0, 5, b);
+    return run_pruned(p->prec, 0, 5, b);
 }
 
 // Device staging for host-resident solves: two input and two output slots.
-size_t host_stage_bytes(ps_plan p) { return 4 * align_up((size_t)p->n * p->n * p->n * p->real_bytes); }
+size_t host_stage_bytes(ps_plan p) { return 4 * align_up(cells(p) * p->real_bytes); }
 
 const char* prec_name(ps_precision p)
 {
@@ -337,15 +355,20 @@ int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || p
 
 // Whether variant v of a pass runs the radix-32-based plan family.
 bool variant_needs_family1(int pass, int v) { return pass == 2 ? v == 2 : (v & 1) != 0; }
-bool family1_available(ps_plan p) { return ps::has_family1(p->P) && p->prec != PS_F32_SPLIT; }
+// Whether the axis a pass transforms has the radix-32-based family.
+bool family1_available(ps_plan p, int pass)
+{
+    const int axis = pass == 2 ? 2 : (pass == 1 || pass == 3) ? 1 : 0;
+    return ps::has_family1(axis_pad(p, axis)) && p->prec != PS_F32_SPLIT;
+}
 
 // Runs passes [lo, hi) of a pruned plan's pipeline with its arithmetic.
-hipError_t run_pruned(ps_precision prec, int P, int lo, int hi, const ps::PrunedBufs& b)
+hipError_t run_pruned(ps_precision prec, int lo, int hi, const ps::PrunedBufs& b)
 {
-    if (prec == PS_F64) return ps::pruned_run_f64(P, lo, hi, b);
-    if (prec == PS_F32_SPLIT) return b.var.mterms == 3 ? ps::pruned_run_split3(P, lo, hi, b)
-                                                       : ps::pruned_run_split6(P, lo, hi, b);
-    return ps::pruned_run_f32(P, lo, hi, b);
+    if (prec == PS_F64) return ps::pruned_run_f64(lo, hi, b);
+    if (prec == PS_F32_SPLIT) return b.var.mterms == 3 ? ps::pruned_run_split3(lo, hi, b)
+                                                       : ps::pruned_run_split6(lo, hi, b);
+    return ps::pruned_run_f32(lo, hi, b);
 }
 
 int* variant_slot(ps::PrunedVariant& v, int pass)
@@ -359,8 +382,21 @@ int* variant_slot(ps::PrunedVariant& v, int pass)
     }
 }
 
-// Tuning cache: one line per (P, precision): "P prec x y z yi xc".
-bool read_tuning(const char* path, int P, ps_precision prec, ps::PrunedVariant& v)
+// Whether `variant` is a kernel variant of `pass` that this plan can run.
+bool variant_ok(ps_plan p, int pass, int variant)
+{
+    if (variant < 0 || variant >= num_variants(pass)) return false;
+    if (variant_needs_family1(pass, variant) && !family1_available(p, pass)) return false;
+    // boxes run the one-tile-per-workgroup kernels only
+    if (p->box && (pass == 1 || pass == 3) && (variant & 2)) return false;
+    if (p->box && pass == 2 && variant >= 3) return false;
+    return true;
+}
+
+// Tuning cache: one line per (P, precision): "P prec x y z yi xc".  A line
+// whose variants this plan cannot run is ignored; the split product-term
+// count (not part of the line) is kept.
+bool read_tuning(const char* path, ps_plan p)
 {
     std::ifstream f(path);
     if (!f) return false;
@@ -370,12 +406,14 @@ bool read_tuning(const char* path, int P, ps_precision prec, ps::PrunedVariant& 
         std::istringstream is(line);
         int pp;
         std::string pr;
-        ps::PrunedVariant t;
-        if (!(is >> pp >> pr >> t.x_fam >> t.y_fam >> t.zmode >> t.yi_fam >> t.xc_fam)) continue;
-        if (pp == P && pr == prec_name(prec)) {
-            v = t;  // the last matching line wins
-            found = true;
-        }
+        int v[5];
+        if (!(is >> pp >> pr >> v[0] >> v[1] >> v[2] >> v[3] >> v[4])) continue;
+        if (pp != p->P || pr != prec_name(p->prec)) continue;
+        bool ok = true;
+        for (int k = 0; k < 5; ++k) ok = ok && variant_ok(p, k, v[k]);
+        if (!ok) continue;
+        for (int k = 0; k < 5; ++k) *variant_slot(p->var, k) = v[k];  // the last valid matching line wins
+        found = true;
     }
     return found;
 }
@@ -421,49 +459,80 @@ const char* ps_status_str(ps_status s)
 
 const char* ps_last_error(void) { return g_last_error.c_str(); }
 
-ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, const char* tune_cache)
+}  // extern "C"
+
+namespace {
+
+// A plan for nx x ny x nz cells of spacings dx, dy, dz (a cube when the
+// three lengths agree).
+ps_status create_plan(ps_plan* out, int nx, int ny, int nz, double dx, double dy, double dz, ps_precision prec,
+                      const char* tune_cache)
 {
     if (!out) return fail(PS_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(PS_ERR_INVALID, "dx must be positive and finite");
+    for (double d : {dx, dy, dz})
+        if (!(d > 0.0) || !std::isfinite(d)) return fail(PS_ERR_INVALID, "cell spacings must be positive and finite");
     if ((int)prec < (int)PS_F64 || (int)prec > (int)PS_F32_PLAIN)
         return fail(PS_ERR_INVALID, "unknown precision " + std::to_string((int)prec));
-    if (n <= 0) return fail(PS_ERR_INVALID, "n must be positive");
-    if (!supported_n(n))
-        return fail(PS_ERR_UNSUPPORTED, "n = " + std::to_string(n) +
-                                            " unsupported (2n must be 16 m <= 1024 with m having no prime factor above 5)");
+    for (int n : {nx, ny, nz}) {
+        if (n <= 0) return fail(PS_ERR_INVALID, "cell counts must be positive");
+        if (!supported_n(n))
+            return fail(PS_ERR_UNSUPPORTED,
+                        "n = " + std::to_string(n) +
+                            " unsupported (2n must be 16 m <= 1024 with m having no prime factor above 5)");
+    }
+    const bool box = !(nx == ny && ny == nz);
+    if (box && is_plain(prec)) return fail(PS_ERR_UNSUPPORTED, "the plain method is built for cubes only");
     ps_plan p = new (std::nothrow) ps_plan_s();
     if (!p) return fail(PS_ERR_INVALID, "out of host memory");
-    p->n = n;
-    p->P = 2 * n;
-    p->H = n + 1;
+    p->n = nx;
+    p->P = 2 * nx;
+    p->H = nx + 1;
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->box = box;
     p->dx = dx;
-    p->dy = dx;
-    p->dz = dx;
+    p->dy = dy;
+    p->dz = dz;
     p->prec = prec;
     p->real_bytes = is_f64(prec) ? 8 : 4;
     if (!ps::host_radices(p->P, p->radices)) {
         delete p;
         return fail(PS_ERR_UNSUPPORTED, "no radix plan");
     }
-    const std::vector<int> inv(p->radices.rbegin(), p->radices.rend());
-    const auto tf = plan_table(p->radices), ti = plan_table(inv);
-    std::vector<int> fwd1;
-    ps::host_radices(p->P, fwd1, 1);
-    const std::vector<int> inv1(fwd1.rbegin(), fwd1.rend());
-    const auto tf1 = plan_table(fwd1), ti1 = plan_table(inv1);
-    if (is_f64(prec)) {
-        append_table<double>(p->tables, p->tw_f, tf);
-        append_table<double>(p->tables, p->tw_i, ti);
-        append_table<double>(p->tables, p->tw_f1, tf1);
-        append_table<double>(p->tables, p->tw_i1, ti1);
-        p->tw_f64 = p->tw_f;
-    } else {
-        append_table<float>(p->tables, p->tw_f, tf);
-        append_table<float>(p->tables, p->tw_i, ti);
-        append_table<float>(p->tables, p->tw_f1, tf1);
-        append_table<float>(p->tables, p->tw_i1, ti1);
-        append_table<double>(p->tables, p->tw_f64, tf);
+    // twiddle tables per distinct axis length
+    for (int a = 0; a < 3; ++a) {
+        const int Pa = axis_pad(p, a);
+        int same = -1;
+        for (int b = 0; b < a && same < 0; ++b)
+            if (axis_pad(p, b) == Pa) same = b;
+        if (same >= 0) {
+            p->tw_f[a] = p->tw_f[same];
+            p->tw_i[a] = p->tw_i[same];
+            p->tw_f1[a] = p->tw_f1[same];
+            p->tw_i1[a] = p->tw_i1[same];
+            p->tw_f64[a] = p->tw_f64[same];
+            continue;
+        }
+        std::vector<int> fwd, fwd1;
+        ps::host_radices(Pa, fwd);
+        ps::host_radices(Pa, fwd1, 1);
+        const std::vector<int> inv(fwd.rbegin(), fwd.rend()), inv1(fwd1.rbegin(), fwd1.rend());
+        const auto tf = plan_table(fwd), ti = plan_table(inv), tf1 = plan_table(fwd1), ti1 = plan_table(inv1);
+        if (is_f64(prec)) {
+            append_table<double>(p->tables, p->tw_f[a], tf);
+            append_table<double>(p->tables, p->tw_i[a], ti);
+            append_table<double>(p->tables, p->tw_f1[a], tf1);
+            append_table<double>(p->tables, p->tw_i1[a], ti1);
+            p->tw_f64[a] = p->tw_f[a];
+        } else {
+            append_table<float>(p->tables, p->tw_f[a], tf);
+            append_table<float>(p->tables, p->tw_i[a], ti);
+            append_table<float>(p->tables, p->tw_f1[a], tf1);
+            append_table<float>(p->tables, p->tw_i1[a], ti1);
+            append_table<double>(p->tables, p->tw_f64[a], tf);
+        }
     }
     if (prec == PS_F32_SPLIT) {
         const auto st = split_dft16_table();
@@ -474,32 +543,41 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     // Default variants, as measured fastest per pass on MI355X: wave-owned
     // z pass; where the radix-32-based family exists (P = 512, 1024) it wins
     // for the forward y pass and, in FP32, the z pass (its persistent,
-    // prefetching form), while the x passes keep the radix-16-based family;
+    // prefetching form), while the x passes keep the radix-16-based family
+    // (except FP64 at P = 1024, whose forward x pass is faster on radix 32);
     // at P = 1024 the inverse y pass runs persistent (radix-32 family in
     // FP32, radix-16 in FP64).  Split plans keep the radix-16 stages (their
-    // matrix-core DFT-16); at P = 1024 their workgroup-synchronised z pass is
-    // faster.
+    // matrix-core DFT-16) and the wave-owned z pass, except at P = 768,
+    // where the workgroup-synchronised one is faster.  Boxes take the
+    // one-tile-per-workgroup forms, per axis length.
+    const int Py = axis_pad(p, 1), Pz = axis_pad(p, 2);
     if (prec == PS_F32_SPLIT) {
-        p->var.zmode = p->P >= 1024 ? 0 : 1;
+        p->var.zmode = Pz == 768 ? 0 : 1;
         p->var.mterms = 6;
+    } else if (box) {
+        p->var.y_fam = ps::has_family1(Py) ? 1 : 0;
+        p->var.zmode = ps::has_family1(Pz) && !(prec == PS_F64 && Pz >= 1024) ? 2 : 1;
     } else if (ps::has_family1(p->P)) {
         p->var.y_fam = 1;
         p->var.zmode = prec == PS_F64 ? (p->P >= 1024 ? 1 : 2) : 3;
         if (p->P >= 1024) p->var.yi_fam = prec == PS_F64 ? 2 : 3;  // persistent inverse y pass
+        if (p->P >= 1024 && prec == PS_F64) p->var.x_fam = 1;
     } else {
         p->var.zmode = 1;
     }
-    if (tune_cache && !is_plain(prec)) read_tuning(tune_cache, p->P, prec, p->var);
-    const size_t N = n, P = p->P, H = p->H, r = p->real_bytes, c = 2 * r;
+    if (tune_cache && !is_plain(prec) && !box) read_tuning(tune_cache, p);
+    const size_t Ny = ny, Nz = nz, Hx = nx + 1, Hy = ny + 1, Hz = nz + 1;
+    const size_t r = p->real_bytes, c = 2 * r;
     size_t off = 0;
     p->off_tab = off;
     p->tab_bytes = align_up(p->tables.size());
     off += p->tab_bytes;
     p->off_ghat = off;
-    p->ghat_bytes = H * H * H * r;
+    p->ghat_bytes = Hx * Hy * Hz * r;
     off += align_up(p->ghat_bytes);
-    const size_t gscr = H * H * H * 8;
+    const size_t gscr = Hx * Hy * Hz * 8;
     if (is_plain(prec)) {
+        const size_t P = p->P, H = p->H;
         p->off_pad = off;
         off += align_up(P * P * P * r);
         p->off_spec = off;
@@ -508,8 +586,8 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
         p->off_gscr = p->off_spec;
     } else {
         p->off_t1 = off;
-        const size_t hp = (H + 15) / 16 * 16;
-        const size_t t1 = std::max(H, hp) * N * N * c, t2 = H * P * N * c;
+        const size_t hp = (Hx + 15) / 16 * 16;
+        const size_t t1 = std::max(Hx, hp) * Nz * Ny * c, t2 = Hx * (2 * Ny) * Nz * c;
         off += align_up(t1);
         p->off_t2 = off;
         off += align_up(t2);
@@ -525,6 +603,21 @@ ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, cons
     p->ws_bytes = off;
     *out = p;
     return PS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status ps_plan_create(ps_plan* out, int n, double dx, ps_precision prec, const char* tune_cache)
+{
+    return create_plan(out, n, n, n, dx, dx, dx, prec, tune_cache);
+}
+
+ps_status ps_plan_create_box(ps_plan* out, int nx, int ny, int nz, double dx, double dy, double dz,
+                             ps_precision prec, const char* tune_cache)
+{
+    return create_plan(out, nx, ny, nz, dx, dy, dz, prec, tune_cache);
 }
 
 ps_status ps_plan_workspace_bytes(ps_plan p, size_t* bytes)
@@ -550,6 +643,9 @@ ps_status ps_plan_query(ps_plan p, ps_plan_info* info)
     info->workspace_bytes = p->ws_bytes;
     info->ghat_bytes = p->ghat_bytes;
     info->ready = p->ready ? 1 : 0;
+    info->nx = p->nx;
+    info->ny = p->ny;
+    info->nz = p->nz;
     for (size_t i = 0; i < p->radices.size() && i < 7; ++i) info->radices[i] = p->radices[i];
     if (!is_plain(p->prec)) {
         info->t1_offset = p->off_t1;
@@ -579,19 +675,22 @@ ps_status ps_green_build(ps_plan p, void* d_workspace, double G, double self_coe
     e = hipMemcpyAsync(ws + p->off_tab, p->tables.data(), p->tables.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return device_fail(e, "table upload");
     ps::GreenBufs gb;
+    gb.nx = p->nx;
+    gb.ny = p->ny;
+    gb.nz = p->nz;
     gb.g1 = reinterpret_cast<double*>(ws + p->off_gscr);
     gb.ghat = ws + p->off_ghat;
-    gb.twf64 = ws + p->off_tab + p->tw_f64;
+    for (int a = 0; a < 3; ++a) gb.twf64[a] = ws + p->off_tab + p->tw_f64[a];
     gb.dx = p->dx;
     gb.sy = p->dy / p->dx;
     gb.sz = p->dz / p->dx;
     gb.self_value = self_value(p->dx, p->dy, p->dz, self_coeff);
-    const double P3 = (double)p->P * p->P * p->P;
+    const double P3 = (double)axis_pad(p, 0) * axis_pad(p, 1) * axis_pad(p, 2);
     gb.scale = G * p->dx * p->dy * p->dz / P3;
     gb.out_f32 = !is_f64(p->prec);
     gb.plain_layout = is_plain(p->prec);
     gb.stream = st;
-    e = ps::green_run(p->P, gb);
+    e = ps::green_run(gb);
     if (e != hipSuccess) return device_fail(e, "kernel build launch");
     p->ws = ws;
     ps::SolveRec rec{};
@@ -615,7 +714,7 @@ ps_status ps_solve(ps_plan p, const void* d_rho, void* d_phi, void* stream)
     if (!d_rho || !d_phi) return fail(PS_ERR_INVALID, "rho and phi must be non-NULL");
     if ((uintptr_t)d_rho % p->real_bytes || (uintptr_t)d_phi % p->real_bytes)
         return fail(PS_ERR_INVALID, "rho and phi must be aligned to their element size");
-    const size_t bytes = (size_t)p->n * p->n * p->n * p->real_bytes;
+    const size_t bytes = cells(p) * p->real_bytes;
     if (overlap(d_rho, bytes, d_phi, bytes)) return fail(PS_ERR_INVALID, "rho and phi overlap");
     if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
     const hipError_t e = enqueue_solve(p, d_rho, d_phi, (hipStream_t)stream);
@@ -637,12 +736,19 @@ ps_status ps_solve_host(ps_plan p, const void* const* h_rho, void* const* h_phi,
     if (ps_status s = check_plan(p)) return s;
     if (!h_rho || !h_phi) return fail(PS_ERR_INVALID, "rho and phi lists must be non-NULL");
     if (count <= 0) return fail(PS_ERR_INVALID, "count must be positive");
-    const size_t bytes = (size_t)p->n * p->n * p->n * p->real_bytes;
+    const size_t bytes = cells(p) * p->real_bytes;
     for (int i = 0; i < count; ++i) {
         if (!h_rho[i] || !h_phi[i]) return fail(PS_ERR_INVALID, "solve " + std::to_string(i) + ": NULL array");
         if (overlap(h_rho[i], bytes, h_phi[i], bytes))
             return fail(PS_ERR_INVALID, "solve " + std::to_string(i) + ": rho and phi overlap");
     }
+    // the download of one solve runs while later uploads read their inputs:
+    // no output may overlap another solve's input or output
+    for (int i = 0; i < count; ++i)
+        for (int j = 0; j < count; ++j)
+            if (j != i && (overlap(h_phi[i], bytes, h_rho[j], bytes) || overlap(h_phi[i], bytes, h_phi[j], bytes)))
+                return fail(PS_ERR_INVALID, "output of solve " + std::to_string(i) + " overlaps an array of solve " +
+                                                std::to_string(j));
     if (!d_stage) return fail(PS_ERR_INVALID, "staging memory is NULL");
     if ((uintptr_t)d_stage % ALIGN) return fail(PS_ERR_INVALID, "staging memory must be 256-byte aligned");
     if (stage_bytes < host_stage_bytes(p)) return fail(PS_ERR_INVALID, "staging memory smaller than ps_host_stage_bytes");
@@ -692,6 +798,17 @@ ps_status ps_solve_host(ps_plan p, const void* const* h_rho, void* const* h_phi,
     return PS_OK;
 }
 
+ps_status ps_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream)
+{
+    if (!d_src || !d_dst) return fail(PS_ERR_INVALID, "src and dst must be non-NULL");
+    if ((uintptr_t)d_src % 16 || (uintptr_t)d_dst % 16 || bytes % 16)
+        return fail(PS_ERR_INVALID, "src, dst and bytes must be multiples of 16");
+    if (overlap(d_src, bytes, d_dst, bytes)) return fail(PS_ERR_INVALID, "src and dst overlap");
+    const hipError_t e = ps::stream_copy(d_src, d_dst, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "copy launch");
+    return PS_OK;
+}
+
 ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void* stream)
 {
     if (ps_status s = check_plan(p)) return s;
@@ -704,7 +821,7 @@ ps_status ps_debug_pass(ps_plan p, int pass, const void* d_in, void* d_out, void
     ps::PrunedBufs b = pruned_bufs(p, nullptr, nullptr, st);
     b.in[pass] = d_in;
     b.out[pass] = d_out;
-    hipError_t e = run_pruned(p->prec, p->P, pass, pass + 1, b);
+    hipError_t e = run_pruned(p->prec, pass, pass + 1, b);
     if (e != hipSuccess) return device_fail(e, "pass launch");
     return PS_OK;
 }
@@ -721,10 +838,10 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
     }
     if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..5");
     if (variant < 0 || variant >= num_variants(pass)) return fail(PS_ERR_INVALID, "variant out of range");
-    if (variant_needs_family1(pass, variant) && !family1_available(p))
+    if (variant_needs_family1(pass, variant) && !family1_available(p, pass))
         return fail(PS_ERR_UNSUPPORTED, "this plan has no radix-32 plan family");
-    if (pass == 2 && variant >= 3 && p->prec == PS_F32_SPLIT)
-        return fail(PS_ERR_UNSUPPORTED, "split plans have no persistent z pass");
+    if (!variant_ok(p, pass, variant))
+        return fail(PS_ERR_UNSUPPORTED, "boxes run the one-tile-per-workgroup kernels (no persistent variants)");
     *variant_slot(p->var, pass) = variant;
     return PS_OK;
 }
@@ -764,14 +881,13 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
     for (int pass = 0; pass < 5 && rc == PS_OK; ++pass) {
         float best_ms = 1e30f;
         for (int v = 0; v < num_variants(pass); ++v) {
-            if (variant_needs_family1(pass, v) && !family1_available(p)) continue;
-            if (pass == 2 && v >= 3 && p->prec == PS_F32_SPLIT) continue;
+            if (!variant_ok(p, pass, v)) continue;
             *variant_slot(b.var, pass) = v;
             const int reps = 5;
             float ms = 0.f;
             for (int r = 0; r <= reps && rc == PS_OK; ++r) {
                 hipEventRecord(e0, st);
-                e = run_pruned(p->prec, p->P, pass, pass + 1, b);
+                e = run_pruned(p->prec, pass, pass + 1, b);
                 hipEventRecord(e1, st);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float t = 0.f;
@@ -790,7 +906,7 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
     hipEventDestroy(e1);
     if (rc != PS_OK) return rc;
     p->var = best;
-    if (cache_path && !write_tuning(cache_path, p->P, p->prec, best))
+    if (cache_path && !p->box && !write_tuning(cache_path, p->P, p->prec, best))
         return fail(PS_ERR_INVALID, std::string("cannot write tuning cache ") + cache_path);
     return PS_OK;
 }
@@ -816,11 +932,11 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
             if (plans[j] == p) return fail(PS_ERR_INVALID, who + ": a plan may appear once per batch");
     }
     for (int i = 0; i < count; ++i) {
-        const size_t bi = (size_t)plans[i]->n * plans[i]->n * plans[i]->n * plans[i]->real_bytes;
+        const size_t bi = cells(plans[i]) * plans[i]->real_bytes;
         if (overlap(d_rho[i], bi, d_phi[i], bi)) return fail(PS_ERR_INVALID, "rho and phi overlap");
         for (int j = 0; j < count; ++j) {
             if (j == i) continue;
-            const size_t bj = (size_t)plans[j]->n * plans[j]->n * plans[j]->n * plans[j]->real_bytes;
+            const size_t bj = cells(plans[j]) * plans[j]->real_bytes;
             if (overlap(d_phi[i], bi, d_phi[j], bj) || overlap(d_phi[i], bi, d_rho[j], bj))
                 return fail(PS_ERR_INVALID, "output of solve " + std::to_string(i) + " overlaps another array");
         }
@@ -829,12 +945,13 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
         if (!plans[i]->ready) return fail(PS_ERR_NOT_READY, "solve " + std::to_string(i) + ": call ps_green_build first");
     hipStream_t st = (hipStream_t)stream;
     ps_plan head = plans[0];
-    // Members sorted by length (largest first), then by kernel variants, so
-    // that per pass every run of equal-length members with the same kernel
-    // is one launch over their adjacent records.
+    // Members sorted by size (largest first) and shape, then by kernel
+    // variants, so that per pass every run of equal-shape members with the
+    // same kernel is one launch over their adjacent records.
     auto vkey = [&](int i) {
         const ps::PrunedVariant& v = plans[i]->var;
-        return std::array<int, 7>{-plans[i]->P, v.x_fam, v.y_fam, v.zmode, v.yi_fam, v.xc_fam, v.mterms};
+        return std::array<int, 10>{-plans[i]->nx * plans[i]->ny * plans[i]->nz, -plans[i]->nz, -plans[i]->ny,
+                                  -plans[i]->nx, v.x_fam, v.y_fam, v.zmode, v.yi_fam, v.xc_fam, v.mterms};
     };
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -850,7 +967,7 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
         for (int x : vkey(i)) sig.push_back((uintptr_t)(intptr_t)x);
     }
     auto* dlist = reinterpret_cast<ps::SolveRec*>(head->ws + head->off_batch);
-    // per pass, runs [k0, k1) of equal length and equal kernel variant
+    // per pass, runs [k0, k1) of equal shape and equal kernel variant
     std::vector<std::pair<int, int>> groups[5];
     size_t most = 1;
     for (int pass = 0; pass < 5; ++pass) {
@@ -859,7 +976,8 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
             int k1 = k0 + 1;
             while (k1 < count) {
                 ps::PrunedVariant v1 = plans[order[k1]]->var;
-                if (plans[order[k1]]->P != plans[order[k0]]->P ||
+                const ps_plan a = plans[order[k0]], c = plans[order[k1]];
+                if (c->nx != a->nx || c->ny != a->ny || c->nz != a->nz ||
                     *variant_slot(v1, pass) != *variant_slot(v0, pass) || v1.mterms != v0.mterms)
                     break;
                 ++k1;
@@ -908,7 +1026,7 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
             ps::PrunedBufs b = pruned_bufs(p0, nullptr, nullptr, sg);
             b.list = dlist + gr[g].first;
             b.count = gr[g].second - gr[g].first;
-            e = run_pruned(prec, p0->P, pass, pass + 1, b);
+            e = run_pruned(prec, pass, pass + 1, b);
             if (e == hipSuccess && g > 0) e = hipEventRecord(head->join[g - 1], sg);
         }
         for (size_t g = 1; g < gr.size() && e == hipSuccess; ++g) e = hipStreamWaitEvent(st, head->join[g - 1], 0);

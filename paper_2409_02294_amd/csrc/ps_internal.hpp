@@ -18,8 +18,9 @@ namespace ps {
 // the persistent form with a one-tile prefetch.  zmode: 0 workgroup-synchronised z pass,
 // 1 wave-owned pencils (family 0), 2 wave-owned pencils (family 1),
 // 3 persistent wave-owned pencils with a one-tile prefetch (family 1 where
-// it exists, else family 0; not for split plans), 4 the same on family 0
-// with fewer pencils per wavefront (one at P = 1024).
+// it exists, else family 0; split plans: family 0), 4 the same on family 0
+// with fewer pencils per wavefront (one at P = 1024).  Boxes take the
+// one-tile-per-workgroup variants only (y: 0, 1; z: 0, 1, 2).
 struct PrunedVariant {
     int x_fam = 0, y_fam = 0, zmode = 0, yi_fam = 0, xc_fam = 0;
     int mterms = 0;  // 0: vector-ALU DFTs; 3 or 6: split-bf16 matrix-core radix-16 DFTs (float only)
@@ -34,6 +35,12 @@ constexpr int NUM_ZMODES = 5;
 struct PrunedBufs {
     const SolveRec* list = nullptr;
     int count = 1;
+    // padded length of each axis (x, y, z); box = false: a cube, every axis
+    // of length px, run by the kernels built for cubes; box = true: the
+    // kernels built for boxes, with the extents nx, ny, nz
+    int px = 0, py = 0, pz = 0;
+    bool box = false;
+    int nx = 0, ny = 0, nz = 0;
     const void* in[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     void* out[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     const unsigned short* stab = nullptr;  // split-bf16 DFT-16 matrix pieces (mterms > 0)
@@ -42,17 +49,20 @@ struct PrunedBufs {
 };
 
 // Runs passes [lo, hi) of the pruned pipeline (0 x_r2c, 1 y_fwd, 2 z_conv,
-// 3 y_inv, 4 x_c2r).  Returns hipErrorInvalidValue for an unsupported P.
-hipError_t pruned_run_f32(int P, int lo, int hi, const PrunedBufs& b);
-hipError_t pruned_run_f64(int P, int lo, int hi, const PrunedBufs& b);
-hipError_t pruned_run_split6(int P, int lo, int hi, const PrunedBufs& b);
-hipError_t pruned_run_split3(int P, int lo, int hi, const PrunedBufs& b);
+// 3 y_inv, 4 x_c2r), each on its axis's padded length.  Returns
+// hipErrorInvalidValue for an unsupported length or a variant boxes lack.
+hipError_t pruned_run_f32(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_f64(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split6(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split3(int lo, int hi, const PrunedBufs& b);
 
-// Transformed-kernel build (double precision throughout).
+// Transformed-kernel build (double precision throughout), on a box of
+// nx x ny x nz cells (a cube when all three are equal).
 struct GreenBufs {
-    double* g1;          // [H][H][H] scratch
+    int nx, ny, nz;      // cells per axis; padded lengths 2 nx, 2 ny, 2 nz
+    double* g1;          // [Hx][Hz][Hy] scratch
     void* ghat;          // output, float or double
-    const void* twf64;   // forward-plan twiddles in double
+    const void* twf64[3];  // forward-plan twiddles in double, per axis
     double dx;           // x spacing
     double sy, sz;       // y and z spacings over dx (1 for cubic cells)
     double self_value;   // K(0)
@@ -61,7 +71,7 @@ struct GreenBufs {
     bool plain_layout;   // [kz][ky][kx] instead of [kx][ky][kz]
     hipStream_t stream;
 };
-hipError_t green_run(int P, const GreenBufs& b);
+hipError_t green_run(const GreenBufs& b);
 
 // The plain method: materialised padded grid and full half spectrum.
 struct PlainBufs {
@@ -76,6 +86,9 @@ struct PlainBufs {
 };
 hipError_t plain_run_f32(int P, const PlainBufs& b);
 hipError_t plain_run_f64(int P, const PlainBufs& b);
+
+// Plain device copy of `bytes` (a multiple of 16; 16-byte aligned arrays).
+hipError_t stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 
 // Radix plans (forward; the inverse is the reverse) for a supported P and
 // plan family; family 1 falls back to family 0 where it does not exist.

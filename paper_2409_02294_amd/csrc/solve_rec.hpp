@@ -14,17 +14,21 @@
 
 namespace ps {
 
+// Twiddle tables are per axis (x, y, z: index 0, 1, 2); a cubic solve points
+// all three at one set.  nx, ny, nz are the box's cell counts, read by the
+// kernels built for boxes (a cubic kernel uses its compile-time length).
 struct SolveRec {
-    const PS_GLOBAL void* rho;   // N^3 real
-    PS_GLOBAL void* phi;         // N^3 real
-    PS_GLOBAL void* t1;          // T1 [H][N][N] complex; later T4 [N][N][HP]
-    PS_GLOBAL void* t2;          // T2 [H][P][N] complex
-    PS_GLOBAL void* t3;          // T3 [H][N][P] complex
-    const PS_GLOBAL void* ghat;  // [H][H][H] real octant, scaled
-    const PS_GLOBAL void* twf;   // forward-plan twiddles, radix-16-based family
-    const PS_GLOBAL void* twi;   // inverse-plan twiddles, radix-16-based family
-    const PS_GLOBAL void* twf1;  // forward-plan twiddles, radix-32-based family (where it exists)
-    const PS_GLOBAL void* twi1;  // inverse-plan twiddles, radix-32-based family
+    const PS_GLOBAL void* rho;      // nz x ny x nx real
+    PS_GLOBAL void* phi;            // nz x ny x nx real
+    PS_GLOBAL void* t1;             // T1 [Hx][nz][ny] complex; later T4 [nz][ny][HPx]
+    PS_GLOBAL void* t2;             // T2 [Hx][Py][nz] complex
+    PS_GLOBAL void* t3;             // T3 [Hx][nz][Py] complex
+    const PS_GLOBAL void* ghat;     // [Hx][Hy][Hz] real octant, scaled
+    const PS_GLOBAL void* twf[3];   // forward-plan twiddles per axis, radix-16-based family
+    const PS_GLOBAL void* twi[3];   // inverse-plan twiddles per axis, radix-16-based family
+    const PS_GLOBAL void* twf1[3];  // forward-plan twiddles per axis, radix-32-based family (where it exists)
+    const PS_GLOBAL void* twi1[3];  // inverse-plan twiddles per axis, radix-32-based family
+    int nx, ny, nz, pad_;
 };
 
 }  // namespace ps

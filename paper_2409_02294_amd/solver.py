@@ -41,7 +41,8 @@ SUPPORTED_N = (8, 16, 24, 32, 40, 48, 64, 72, 80, 96, 120, 128, 144, 160, 192, 2
 
 EXPORTS = ("ps_plan_create", "ps_plan_workspace_bytes", "ps_plan_query", "ps_green_build", "ps_solve",
            "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass",
-           "ps_plan_set_variant", "ps_autotune", "ps_host_stage_bytes", "ps_solve_host", "ps_plan_set_spacing")
+           "ps_plan_set_variant", "ps_autotune", "ps_host_stage_bytes", "ps_solve_host", "ps_plan_set_spacing",
+           "ps_stream_copy", "ps_plan_create_box")
 
 
 class PSError(RuntimeError):
@@ -56,7 +57,8 @@ class PlanInfo(ctypes.Structure):
                 ("ready", ctypes.c_int), ("radices", ctypes.c_int * 8),
                 ("t1_offset", ctypes.c_size_t), ("t2_offset", ctypes.c_size_t), ("t3_offset", ctypes.c_size_t),
                 ("variant", ctypes.c_int * 5),
-                ("split_terms", ctypes.c_int), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+                ("split_terms", ctypes.c_int), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -77,6 +79,7 @@ def load() -> ctypes.CDLL:
     vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     sig = {
         "ps_plan_create": ([ctypes.POINTER(vp), i, d, i, ctypes.c_char_p], i),
+        "ps_plan_create_box": ([ctypes.POINTER(vp), i, i, i, d, d, d, i, ctypes.c_char_p], i),
         "ps_plan_workspace_bytes": ([vp, ctypes.POINTER(sz)], i),
         "ps_plan_query": ([vp, ctypes.POINTER(PlanInfo)], i),
         "ps_green_build": ([vp, vp, d, d, vp], i),
@@ -91,6 +94,7 @@ def load() -> ctypes.CDLL:
         "ps_plan_set_variant": ([vp, i, i], i),
         "ps_plan_set_spacing": ([vp, ctypes.c_double, ctypes.c_double], i),
         "ps_autotune": ([vp, vp, ctypes.c_char_p], i),
+        "ps_stream_copy": ([vp, vp, sz, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -121,6 +125,15 @@ def ps_plan_create(n: int, dx: float, precision: int, tune_cache: Optional[str] 
     return h.value
 
 
+def ps_plan_create_box(nx: int, ny: int, nz: int, dx: float, dy: float, dz: float, precision: int,
+                       tune_cache: Optional[str] = None) -> int:
+    h = ctypes.c_void_p()
+    tc = tune_cache.encode() if tune_cache else None
+    _check(load().ps_plan_create_box(ctypes.byref(h), int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
+                                     int(precision), tc), "ps_plan_create_box")
+    return h.value
+
+
 def ps_plan_workspace_bytes(plan: int) -> int:
     b = ctypes.c_size_t()
     _check(load().ps_plan_workspace_bytes(plan, ctypes.byref(b)), "ps_plan_workspace_bytes")
@@ -134,7 +147,7 @@ def ps_plan_query(plan: int) -> Dict:
     return dict(n=info.n, p=info.p, h=info.h, precision=info.precision, dx=info.dx,
                 workspace_bytes=info.workspace_bytes, ghat_bytes=info.ghat_bytes, ready=bool(info.ready),
                 radices=rad, t1_offset=info.t1_offset, t2_offset=info.t2_offset, t3_offset=info.t3_offset, variant=list(info.variant), split_terms=info.split_terms,
-                dy=info.dy, dz=info.dz)
+                dy=info.dy, dz=info.dz, nx=info.nx, ny=info.ny, nz=info.nz)
 
 
 def ps_green_build(plan: int, workspace: int, G: float, self_coeff: float, stream: int) -> None:
@@ -185,6 +198,10 @@ def ps_plan_set_spacing(plan: int, dy: float, dz: float) -> None:
     _check(load().ps_plan_set_spacing(plan, float(dy), float(dz)), "ps_plan_set_spacing")
 
 
+def ps_stream_copy(src: int, dst: int, nbytes: int, stream: int) -> None:
+    _check(load().ps_stream_copy(src, dst, int(nbytes), stream), "ps_stream_copy")
+
+
 def ps_autotune(plan: int, stream: int, cache_path: Optional[str] = None) -> None:
     cp = cache_path.encode() if cache_path else None
     _check(load().ps_autotune(plan, stream, cp), "ps_autotune")
@@ -199,7 +216,9 @@ class Solver:
 
     ``Solver(n, dx, "f32")(rho)`` returns the potential of the ``(n, n, n)``
     density tensor ``rho`` (float64 for f64 precisions, float32 otherwise)
-    as a new tensor, enqueued on torch's current stream.
+    as a new tensor, enqueued on torch's current stream.  ``n`` may also be a
+    box ``(nx, ny, nz)`` (tensors of shape ``(nz, ny, nx)``, a plan from
+    ps_plan_create_box), with ``spacing=(dy, dz)`` as for cubes.
     """
 
     def __init__(self, n: int, dx: Optional[float] = None, precision="f32", G: float = 1.0,
@@ -207,14 +226,20 @@ class Solver:
                  spacing: Optional[tuple] = None):
         import torch
         self.torch = torch
-        self.n = int(n)
+        dims = tuple(int(v) for v in n) if isinstance(n, (tuple, list)) else (int(n),) * 3
+        self.n = dims[0]
+        self.shape = (dims[2], dims[1], dims[0])  # [z][y][x]
         self.dx = float(dx) if dx is not None else 1.0 / self.n
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.dtype = torch.float64 if self.precision in (PS_F64, PS_F64_PLAIN) else torch.float32
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.plan = ps_plan_create(self.n, self.dx, self.precision, tune_cache)
-        if spacing is not None:  # (dy, dz): cells of spacings dx, dy, dz
-            ps_plan_set_spacing(self.plan, spacing[0], spacing[1])
+        if dims[0] == dims[1] == dims[2]:
+            self.plan = ps_plan_create(self.n, self.dx, self.precision, tune_cache)
+            if spacing is not None:  # (dy, dz): cells of spacings dx, dy, dz
+                ps_plan_set_spacing(self.plan, spacing[0], spacing[1])
+        else:
+            dy, dz = spacing if spacing is not None else (self.dx, self.dx)
+            self.plan = ps_plan_create_box(dims[0], dims[1], dims[2], self.dx, dy, dz, self.precision, tune_cache)
         nbytes = ps_plan_workspace_bytes(self.plan)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -229,8 +254,8 @@ class Solver:
         if outs is None:
             outs = [torch.empty_like(r) for r in rhos]
         for t in list(rhos) + list(outs):
-            if t.device.type != "cpu" or t.dtype != self.dtype or tuple(t.shape) != (self.n,) * 3 or not t.is_contiguous():
-                raise ValueError(f"host arrays must be contiguous {self.dtype} CPU tensors of shape {(self.n,) * 3}")
+            if t.device.type != "cpu" or t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+                raise ValueError(f"host arrays must be contiguous {self.dtype} CPU tensors of shape {self.shape}")
         nbytes = ps_host_stage_bytes(self.plan)
         if stage is None:
             stage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -245,8 +270,8 @@ class Solver:
         return ps_plan_query(self.plan)
 
     def _check_tensor(self, t, name):
-        if t.device != self.device or t.dtype != self.dtype or tuple(t.shape) != (self.n,) * 3 or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {(self.n,) * 3} on {self.device}")
+        if t.device != self.device or t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {self.shape} on {self.device}")
 
     def solve(self, rho, out=None):
         torch = self.torch

@@ -110,6 +110,15 @@ def test_calls_on_unbuilt_plan():
         S.ps_plan_destroy(p)
 
 
+def test_stream_copy_contract():
+    lib = S.load()
+    assert lib.ps_stream_copy(None, 0x100000, 16, None) == S.PS_ERR_INVALID
+    assert lib.ps_stream_copy(0x100000, None, 16, None) == S.PS_ERR_INVALID
+    assert lib.ps_stream_copy(0x100008, 0x200000, 16, None) == S.PS_ERR_INVALID   # misaligned
+    assert lib.ps_stream_copy(0x100000, 0x200000, 24, None) == S.PS_ERR_INVALID   # not a multiple of 16
+    assert lib.ps_stream_copy(0x100000, 0x100010, 64, None) == S.PS_ERR_INVALID   # overlap
+
+
 def test_null_plan_and_batch_arguments():
     lib = S.load()
     assert lib.ps_solve(None, 0x100000, 0x10000000, None) == S.PS_ERR_INVALID
@@ -196,9 +205,23 @@ def test_tuning_cache_is_read(tmp_path):
         assert S.ps_plan_query(p)["variant"] == [0, 1, 3, 0, 0]
     finally:
         S.ps_plan_destroy(p)
-    for n, prec, want in [(512, S.PS_F32, [0, 1, 3, 3, 0]), (512, S.PS_F64, [0, 1, 1, 2, 0]),
-                          (256, S.PS_F64, [0, 1, 2, 0, 0]),
-                          (128, S.PS_F32, [0, 0, 1, 0, 0]), (512, S.PS_F32_SPLIT, [0, 0, 0, 0, 0])]:
+    # a split plan keeps its product-term count under a cached line; a line
+    # naming variants the plan cannot run is ignored
+    path.write_text("512 f32_split 0 0 0 0 0\n256 f32 0 0 9 0 0\n512 f32_split 0 1 3 0 0\n")
+    p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32_SPLIT, str(path))
+    try:
+        info = S.ps_plan_query(p)
+        assert info["variant"] == [0, 0, 0, 0, 0] and info["split_terms"] == 6
+    finally:
+        S.ps_plan_destroy(p)
+    p = S.ps_plan_create(128, 1.0 / 128, S.PS_F32, str(path))
+    try:
+        assert S.ps_plan_query(p)["variant"] == [0, 0, 1, 0, 0]  # zmode 9 does not exist: defaults kept
+    finally:
+        S.ps_plan_destroy(p)
+    for n, prec, want in [(512, S.PS_F32, [0, 1, 3, 3, 0]), (512, S.PS_F64, [1, 1, 1, 2, 0]),
+                          (256, S.PS_F64, [0, 1, 2, 0, 0]), (384, S.PS_F32_SPLIT, [0, 0, 0, 0, 0]),
+                          (128, S.PS_F32, [0, 0, 1, 0, 0]), (512, S.PS_F32_SPLIT, [0, 0, 1, 0, 0])]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
         try:
             assert S.ps_plan_query(p)["variant"] == want, (n, prec)
@@ -216,8 +239,9 @@ def test_split_plan_contract():
         assert lib.ps_plan_set_variant(p, 5, 4) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # keeps the radix-16 family
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
-        assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_UNSUPPORTED   # no persistent split z pass
-        assert lib.ps_plan_set_variant(p, 2, 4) == S.PS_ERR_UNSUPPORTED
+        assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_OK   # persistent split z pass (radix-16 family)
+        assert lib.ps_plan_set_variant(p, 2, 4) == S.PS_OK
+        assert lib.ps_plan_set_variant(p, 1, 2) == S.PS_OK   # persistent split y pass
         S.ps_plan_set_variant(p, 5, 3)
         assert S.ps_plan_query(p)["split_terms"] == 3
         assert S.ps_plan_workspace_bytes(p) >= S.ps_plan_workspace_bytes(S.ps_plan_create(256, 1.0 / 256, S.PS_F32))
@@ -245,8 +269,62 @@ def test_host_solve_contract():
         assert lib.ps_solve_host(p, rho, phi, 2, stage, nb - 1, None) == S.PS_ERR_INVALID  # too small
         same = (vp * 2)(ctypes.addressof(host[0]), ctypes.addressof(host[1]))
         assert lib.ps_solve_host(p, rho, same, 2, stage, nb, None) == S.PS_ERR_INVALID    # rho is phi
+        # the output of one solve on another solve's input, or on another output
+        cross = (vp * 2)(ctypes.addressof(host[2]), ctypes.addressof(host[0]))
+        assert lib.ps_solve_host(p, rho, cross, 2, stage, nb, None) == S.PS_ERR_INVALID
+        assert "overlaps an array of solve" in lib.ps_last_error().decode()
+        twice = (vp * 2)(ctypes.addressof(host[2]), ctypes.addressof(host[2]))
+        assert lib.ps_solve_host(p, rho, twice, 2, stage, nb, None) == S.PS_ERR_INVALID
         assert lib.ps_solve_host(p, rho, phi, 2, stage, nb, None) == S.PS_ERR_NOT_READY   # no Green's function
         assert "ps_green_build" in lib.ps_last_error().decode()
     finally:
         S.ps_plan_destroy(p)
         S.ps_plan_destroy(q)
+
+
+def test_box_plan_contract():
+    # boxes of nx x ny x nz cells: argument checks, layout, defaults and the
+    # variants a box may run, all before any HIP call
+    lib = S.load()
+    for dims, status in [((0, 16, 16), S.PS_ERR_INVALID), ((16, -8, 16), S.PS_ERR_INVALID),
+                         ((16, 56, 16), S.PS_ERR_UNSUPPORTED), ((16, 16, 1024), S.PS_ERR_UNSUPPORTED)]:
+        with pytest.raises(S.PSError) as e:
+            S.ps_plan_create_box(*dims, 0.1, 0.1, 0.1, S.PS_F32)
+        assert e.value.status == status
+    for sp in [(0.0, 0.1, 0.1), (0.1, float("nan"), 0.1), (0.1, 0.1, -1.0)]:
+        with pytest.raises(S.PSError) as e:
+            S.ps_plan_create_box(16, 32, 48, *sp, S.PS_F64)
+        assert e.value.status == S.PS_ERR_INVALID
+    for prec in (S.PS_F64_PLAIN, S.PS_F32_PLAIN):
+        with pytest.raises(S.PSError) as e:
+            S.ps_plan_create_box(16, 32, 48, 0.1, 0.1, 0.1, prec)
+        assert e.value.status == S.PS_ERR_UNSUPPORTED
+    nx, ny, nz = 40, 256, 24
+    p = S.ps_plan_create_box(nx, ny, nz, 0.1, 0.2, 0.3, S.PS_F32)
+    try:
+        info = S.ps_plan_query(p)
+        assert (info["nx"], info["ny"], info["nz"]) == (nx, ny, nz)
+        assert (info["dx"], info["dy"], info["dz"]) == (0.1, 0.2, 0.3)
+        assert info["n"] == nx and info["p"] == 2 * nx and info["h"] == nx + 1
+        hx, hpx = nx + 1, (nx + 1 + 15) // 16 * 16
+        assert info["t2_offset"] - info["t1_offset"] >= max(hx, hpx) * nz * ny * 8
+        assert info["t3_offset"] - info["t2_offset"] >= hx * 2 * ny * nz * 8
+        assert info["variant"] == [0, 1, 1, 0, 0]  # radix-32 family for y (P = 512), wave-owned z
+        assert S.ps_host_stage_bytes(p) == 4 * ((nx * ny * nz * 4 + 255) // 256 * 256)
+        assert lib.ps_plan_set_variant(p, 1, 2) == S.PS_ERR_UNSUPPORTED   # persistent y pass: cubes only
+        assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_UNSUPPORTED   # persistent z pass: cubes only
+        assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED   # P = 48 along z: no radix-32 family
+        assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # P = 80 along x: no radix-32 family
+        assert lib.ps_plan_set_variant(p, 3, 1) == S.PS_OK
+        assert lib.ps_solve(p, 0x100000, 0x10000000, None) == S.PS_ERR_NOT_READY
+    finally:
+        S.ps_plan_destroy(p)
+    # equal lengths: exactly the cubic plan
+    a = S.ps_plan_create_box(64, 64, 64, 1 / 64, 1 / 64, 1 / 64, S.PS_F32)
+    b = S.ps_plan_create(64, 1 / 64, S.PS_F32)
+    try:
+        qa, qb = S.ps_plan_query(a), S.ps_plan_query(b)
+        assert qa == qb
+    finally:
+        S.ps_plan_destroy(a)
+        S.ps_plan_destroy(b)

@@ -90,3 +90,22 @@ def test_two_plans_on_two_streams():
     torch.cuda.synchronize()
     for oa, ob in zip(outs_a, outs_b):
         assert torch.equal(oa, ref_a) and torch.equal(ob, ref_b)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split", "f64_plain", "f32_plain"])
+def test_host_solves_match_oracle(prec):
+    # every solve of a host-resident sequence against the FP64 oracle's FFT
+    # convolution of the same (precision-rounded) density
+    import oracle
+    n = 40
+    tol = 1e-12 if prec.startswith("f64") else 1e-6
+    s = S.Solver(n, 1.0 / n, prec)
+    rhos = [r.pin_memory() for r in _densities(n, 3, 6500, s.dtype)]
+    outs = s.solve_host(rhos)
+    torch.cuda.synchronize()
+    for r, o in zip(rhos, outs):
+        ref = oracle.fft_conv(r.double().numpy(), 1.0 / n)
+        got = o.double().numpy()
+        l2, mx = oracle.rel_l2(got, ref), oracle.rel_max(got, ref)
+        print(f"host {prec}: relL2={l2:.3e} relMax={mx:.3e}", flush=True)
+        assert l2 <= tol

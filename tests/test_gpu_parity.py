@@ -298,6 +298,24 @@ def test_persistent_z_pass_n512(prec):
     torch.cuda.empty_cache()
 
 
+def test_split_persistent_passes_n512():
+    # the split form's persistent z and y passes against its one-tile-per-workgroup ones
+    n = 512
+    s = S.Solver(n, 1.0 / n, "f32_split")
+    rho = torch.from_numpy(_blobs512()).to("cuda", torch.float32)
+    for k in range(5):
+        S.ps_plan_set_variant(s.plan, k, 0)
+    base = s(rho).double()
+    for k, v in ((2, 1), (2, 3), (2, 4), (1, 2), (3, 2)):
+        S.ps_plan_set_variant(s.plan, k, v)
+        got = s(rho).double()
+        l2 = float((got - base).norm() / base.norm())
+        print(f"n=512 f32_split pass {k} variant {v}: relL2 vs variant 0 {l2:.2e}", flush=True)
+        assert l2 <= 5e-7
+    del s, rho, base, got
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_variants_agree_n256(prec):
     n = 256
@@ -327,7 +345,7 @@ def test_variants_agree_n256(prec):
     assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 @pytest.mark.parametrize("n", [16, 48, 96, 120])
 @pytest.mark.parametrize("zmode", [0, 1, 3, 4])
 def test_zmodes_match_oracle(prec, n, zmode):
@@ -393,3 +411,23 @@ def test_split_terms_error(n):
     assert errs[3][0] <= 5e-5
     # the six-term products carry more of the operands than the three-term ones
     assert errs[6][0] < errs[3][0]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f32_split"])
+def test_blobs512_full_field_vs_f64_path(prec):
+    # the whole 512^3 field of the single-precision paths against the FP64
+    # path (itself within 1e-12 of the oracle at every size tested), in the
+    # launch configuration the benchmark times
+    n = 512
+    rho64 = _blobs512()
+    s64 = S.Solver(n, 1.0 / n, "f64")
+    s = S.Solver(n, 1.0 / n, prec)
+    r32 = torch.from_numpy(rho64).to("cuda", torch.float32)
+    ref = s64(r32.double())
+    got = s(r32).double()
+    l2 = float((got - ref).norm() / ref.norm())
+    mx = float((got - ref).abs().max() / ref.abs().max())
+    print(f"512^3 full field {prec} vs f64 path: relL2={l2:.3e} relMax={mx:.3e}", flush=True)
+    assert l2 <= 1e-6
+    del s64, s, r32, ref, got
+    torch.cuda.empty_cache()
