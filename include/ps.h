@@ -141,6 +141,23 @@ ps_status ps_green_build(ps_plan p, void *d_workspace, double G, double self_coe
  * PS_ERR_DEVICE if a launch fails; nothing is enqueued on error. */
 ps_status ps_solve(ps_plan p, const void *d_rho, void *d_phi, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ps_solve with
+ * the solve's intermediates in the library's static device scratch instead
+ * of the plan's workspace.  The scratch is one file-scope device array of
+ * 128 MiB per GPU (held until the process ends), enough for the pruned
+ * intermediates up to n = 144 in single precision and n = 96 in double;
+ * larger plans return PS_ERR_UNSUPPORTED, PLAIN plans PS_ERR_UNSUPPORTED.
+ * The plan must be built (its transformed kernel and tables stay in its
+ * workspace).  The call allocates nothing and makes no host-to-device copy:
+ * it enqueues the same kernels as ps_solve, so results equal ps_solve's
+ * bitwise, and it can be captured into a HIP graph.  Every call on one GPU
+ * shares that GPU's scratch, and each solve overwrites all of it that it
+ * reads, so nothing needs clearing; calls that overlap in time on one GPU
+ * (other streams, other host threads) race on the scratch and must be
+ * ordered by the caller. */
+ps_status ps_solve_static(ps_plan p, const void *d_rho, void *d_phi, void *stream);
+
 /* Bytes of caller-owned device staging memory that ps_solve_host needs for
  * this plan: two input and two output slots of n^3 reals (256-byte aligned).
  * Host only, no HIP call. */

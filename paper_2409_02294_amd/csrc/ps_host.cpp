@@ -722,6 +722,41 @@ ps_status ps_solve(ps_plan p, const void* d_rho, void* d_phi, void* stream)
     return PS_OK;
 }
 
+ps_status ps_solve_static(ps_plan p, const void* d_rho, void* d_phi, void* stream)
+{
+    if (ps_status s = check_plan(p)) return s;
+    if (is_plain(p->prec)) return fail(PS_ERR_UNSUPPORTED, "ps_solve_static runs the pruned pipeline only");
+    if (!d_rho || !d_phi) return fail(PS_ERR_INVALID, "rho and phi must be non-NULL");
+    if ((uintptr_t)d_rho % p->real_bytes || (uintptr_t)d_phi % p->real_bytes)
+        return fail(PS_ERR_INVALID, "rho and phi must be aligned to their element size");
+    const size_t bytes = cells(p) * p->real_bytes;
+    if (overlap(d_rho, bytes, d_phi, bytes)) return fail(PS_ERR_INVALID, "rho and phi overlap");
+    // T1/T4, T2 and T3 back to back, each 256-byte aligned
+    const size_t o2 = align_up(p->off_t2 - p->off_t1), o3 = o2 + align_up(p->off_t3 - p->off_t2);
+    const size_t need = o3 + align_up(p->off_t3 - p->off_t2);
+    if (need > ps::STATIC_SCRATCH_BYTES)
+        return fail(PS_ERR_UNSUPPORTED, "this plan needs " + std::to_string(need) +
+                                            " bytes of scratch; the static scratch holds " +
+                                            std::to_string(ps::STATIC_SCRATCH_BYTES));
+    if (!p->ready) return fail(PS_ERR_NOT_READY, "call ps_green_build first");
+    void* scr = nullptr;
+    hipError_t e = ps::static_scratch(&scr);
+    if (e != hipSuccess) return device_fail(e, "static scratch address");
+    unsigned char* s1 = static_cast<unsigned char*>(scr);
+    ps::PrunedBufs b = pruned_bufs(p, d_rho, d_phi, (hipStream_t)stream);
+    b.out[0] = s1;
+    b.in[1] = s1;
+    b.out[1] = s1 + o2;
+    b.in[2] = s1 + o2;
+    b.out[2] = s1 + o3;
+    b.in[3] = s1 + o3;
+    b.out[3] = s1;
+    b.in[4] = s1;
+    e = run_pruned(p->prec, 0, 5, b);
+    if (e != hipSuccess) return device_fail(e, "solve launch");
+    return PS_OK;
+}
+
 ps_status ps_host_stage_bytes(ps_plan p, size_t* bytes)
 {
     if (ps_status s = check_plan(p)) return s;

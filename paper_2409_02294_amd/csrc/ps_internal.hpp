@@ -87,6 +87,13 @@ struct PlainBufs {
 hipError_t plain_run_f32(int P, const PlainBufs& b);
 hipError_t plain_run_f64(int P, const PlainBufs& b);
 
+// Device scratch of solves that allocate nothing (ps_solve_static): a
+// file-scope device array of this many bytes per GPU, held until the process
+// ends.  static_scratch() returns its device address on the current device
+// (looked up once per device).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)128 << 20;
+hipError_t static_scratch(void** out);
+
 // Plain device copy of `bytes` (a multiple of 16; 16-byte aligned arrays).
 hipError_t stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 

@@ -42,7 +42,7 @@ SUPPORTED_N = (8, 16, 24, 32, 40, 48, 64, 72, 80, 96, 120, 128, 144, 160, 192, 2
 EXPORTS = ("ps_plan_create", "ps_plan_workspace_bytes", "ps_plan_query", "ps_green_build", "ps_solve",
            "ps_solve_batched", "ps_plan_destroy", "ps_status_str", "ps_last_error", "ps_debug_pass",
            "ps_plan_set_variant", "ps_autotune", "ps_host_stage_bytes", "ps_solve_host", "ps_plan_set_spacing",
-           "ps_stream_copy", "ps_plan_create_box")
+           "ps_stream_copy", "ps_solve_static", "ps_plan_create_box")
 
 
 class PSError(RuntimeError):
@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
         "ps_plan_set_spacing": ([vp, ctypes.c_double, ctypes.c_double], i),
         "ps_autotune": ([vp, vp, ctypes.c_char_p], i),
         "ps_stream_copy": ([vp, vp, sz, vp], i),
+        "ps_solve_static": ([vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +197,10 @@ def ps_plan_set_variant(plan: int, pass_id: int, variant: int) -> None:
 
 def ps_plan_set_spacing(plan: int, dy: float, dz: float) -> None:
     _check(load().ps_plan_set_spacing(plan, float(dy), float(dz)), "ps_plan_set_spacing")
+
+
+def ps_solve_static(plan: int, rho: int, phi: int, stream: int) -> None:
+    _check(load().ps_solve_static(plan, rho, phi, stream), "ps_solve_static")
 
 
 def ps_stream_copy(src: int, dst: int, nbytes: int, stream: int) -> None:

@@ -328,3 +328,22 @@ def test_box_plan_contract():
     finally:
         S.ps_plan_destroy(a)
         S.ps_plan_destroy(b)
+
+
+def test_static_solve_contract():
+    # the allocation-free solve's checks, all before any HIP call
+    lib = S.load()
+    assert lib.ps_solve_static(None, 0x100000, 0x10000000, None) == S.PS_ERR_INVALID
+    p = S.ps_plan_create(64, 1 / 64, S.PS_F32)
+    q = S.ps_plan_create(160, 1 / 160, S.PS_F32)
+    r = S.ps_plan_create(32, 1 / 32, S.PS_F64_PLAIN)
+    try:
+        assert lib.ps_solve_static(p, None, 0x10000000, None) == S.PS_ERR_INVALID
+        assert lib.ps_solve_static(p, 0x100000, 0x100000 + 64, None) == S.PS_ERR_INVALID   # overlap
+        assert lib.ps_solve_static(p, 0x100000, 0x10000000, None) == S.PS_ERR_NOT_READY
+        assert lib.ps_solve_static(q, 0x100000, 0x10000000, None) == S.PS_ERR_UNSUPPORTED  # beyond the scratch
+        assert "static scratch" in lib.ps_last_error().decode()
+        assert lib.ps_solve_static(r, 0x100000, 0x10000000, None) == S.PS_ERR_UNSUPPORTED  # plain method
+    finally:
+        for h in (p, q, r):
+            S.ps_plan_destroy(h)
