@@ -128,19 +128,31 @@ template <> struct SplitA<0> {
     __device__ __forceinline__ void load(const unsigned short*) {}
 };
 
+typedef float ps_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 ps_bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned ps_u32x4 __attribute__((ext_vector_type(4)));
+
+// The NP bf16 pieces of x[0..7], two elements per 32-bit register as the
+// matrix instruction's operand holds them: each pair is rounded by one
+// packed conversion (round to nearest even), and its residual is formed
+// from the two halves of the packed result (a bf16 value is the top half of
+// the float it rounds to, so shifting or masking recovers it exactly).
 template <int NP> __device__ __forceinline__ void split_pieces(const float* x, ps_bf16x8* out)
 {
-    float r[8];
+    ps_u32x4 w[NP];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = x[i];
+    for (int i = 0; i < 4; ++i) {
+        ps_f32x2 r = {x[2 * i], x[2 * i + 1]};
 #pragma unroll
-    for (int pc = 0; pc < NP; ++pc) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            out[pc][i] = (__bf16)r[i];
-            r[i] = r[i] - (float)out[pc][i];
+        for (int pc = 0; pc < NP; ++pc) {
+            const unsigned u = __builtin_bit_cast(unsigned, __builtin_convertvector(r, ps_bf16x2));
+            w[pc][i] = u;
+            if (pc + 1 < NP)
+                r = ps_f32x2{r[0] - __builtin_bit_cast(float, u << 16), r[1] - __builtin_bit_cast(float, u & 0xffff0000u)};
         }
     }
+#pragma unroll
+    for (int pc = 0; pc < NP; ++pc) out[pc] = __builtin_bit_cast(ps_bf16x8, w[pc]);
 }
 
 // In-place forward (DIR -1) or inverse (DIR +1) DFT-16 of the lane's 8 elements.
@@ -178,8 +190,16 @@ template <int MT, int DIR> __device__ __forceinline__ void dft16_split(float2* v
 }
 
 // LDS row pitch (complex elements) of a length-P pencil with one pad slot
-// every G elements.
-constexpr int pad_pitch(int P, int G) { return P + P / G + 1; }
+// every G elements, for elements of EB bytes.  8-byte elements take
+// P + P/G + 1.  16-byte elements take the next pitch that is 4 mod 8: with
+// the pencil-fastest mapping (8 pencils by 2 offsets in 16 lanes), 16-byte
+// accesses measured free of bank conflicts on gfx950 only at such pitches
+// (8 extra cycles per instruction at 1 mod 16, 4 at 2 mod 16).
+constexpr int pad_pitch(int P, int G, int EB = 8)
+{
+    const int lp = P + P / G + 1;
+    return EB == 16 ? lp + (12 - lp % 8) % 8 : lp;
+}
 constexpr int pad_shift(int r0) { return r0 == 32 ? 5 : 4; }
 
 // MT: 0 = every stage on the vector ALUs; 3 or 6 = radix-16 stages on the
@@ -213,7 +233,7 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0, i
     static constexpr int GS = pad_shift(RP::r[0]);  // log2 of the pad granularity G
     static constexpr int G = 1 << GS;
     static_assert(PITCH == 0 || PITCH >= pad_pitch(P, G), "row pitch below the padded pencil");
-    static constexpr int LP = PITCH > 0 ? PITCH : pad_pitch(P, G);
+    static constexpr int LP = PITCH > 0 ? PITCH : pad_pitch(P, G, (int)sizeof(V));
     static constexpr int LDS_ELEMS = B * LP;
 
     // Twiddle source: the row and column layouts of the plan's table.  A

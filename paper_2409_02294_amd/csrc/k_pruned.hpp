@@ -156,8 +156,8 @@ template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT, bool BOX
     using V = cx<T>;
     // the two plans share one LDS buffer with one row pitch (their pad
     // granularities may differ), so a wavefront's pencils sit in the same rows
-    static constexpr int LPF = pad_pitch(P, 1 << pad_shift(PlanFor<P, FAM>::Fwd::r[0]));
-    static constexpr int LPI = pad_pitch(P, 1 << pad_shift(PlanFor<P, FAM>::Inv::r[0]));
+    static constexpr int LPF = pad_pitch(P, 1 << pad_shift(PlanFor<P, FAM>::Fwd::r[0]), (int)sizeof(V));
+    static constexpr int LPI = pad_pitch(P, 1 << pad_shift(PlanFor<P, FAM>::Inv::r[0]), (int)sizeof(V));
     static constexpr int LPZ = LPF > LPI ? LPF : LPI;
     using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, WAVE, MT, LPZ>;
     using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, WAVE, MT, LPZ>;

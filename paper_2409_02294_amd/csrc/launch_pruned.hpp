@@ -48,7 +48,12 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     using V = cx<T>;
     static constexpr int N = P / 2, H = N + 1;
     static constexpr int ZT = PrunedShape<T>::ZT, ZB = PrunedShape<T>::ZB;
+    // elements per thread: 32 for the radix-32-based family, else 16; the
+    // z pass of split plans also takes 32 (its matrix-core DFT-16 operands
+    // and accumulators need the register budget of half as many threads:
+    // at 16 the compiler spilled and the pass moved 1.4x its bytes)
     static constexpr int E = FAM == 1 ? 32 : 16;
+    static constexpr int EZ = (FAM == 1 || MT > 0) ? 32 : 16;
     static constexpr int NTX = threads_for(8, P, E);
     static constexpr int NTY = threads_for(ZT, P, E);
 
@@ -64,7 +69,7 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     }
     template <bool WAVE> static void z_conv(const PrunedBufs& b)
     {
-        constexpr int NTZ = WAVE ? wave_threads(ZB, P, E) : threads_for(ZB, P, E);
+        constexpr int NTZ = WAVE ? wave_threads(ZB, P, EZ) : threads_for(ZB, P, EZ);
         hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H, b.count), dim3(NTZ), 0, b.stream,
                            static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab);
     }
@@ -125,7 +130,7 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     }
     template <bool WAVE> static void z_conv_box(const PrunedBufs& b)
     {
-        constexpr int NTZ = WAVE ? wave_threads(ZB, P, E) : threads_for(ZB, P, E);
+        constexpr int NTZ = WAVE ? wave_threads(ZB, P, EZ) : threads_for(ZB, P, EZ);
         hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT, true>), dim3(2 * b.ny / ZB, b.nx + 1, b.count),
                            dim3(NTZ), 0, b.stream, static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list,
                            b.stab);
