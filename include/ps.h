@@ -84,6 +84,7 @@ typedef struct {
     int split_terms;        /* PS_F32_SPLIT: split-bf16 product terms per DFT-16 (6 or 3); else 0 */
     double dy, dz;          /* cell spacings along y and z (dx unless set by ps_plan_set_spacing) */
     int nx, ny, nz;         /* cells along x, y, z (all n for a cube; n, p, h and radices describe x) */
+    int z_tile;             /* pruned plans: pencils per z-pass workgroup, 0 = full tile, 1 = half (ps_plan_set_variant pass 6) */
 } ps_plan_info;
 
 /* Create a plan for an n^3 grid of spacing dx (> 0) in the given precision:
@@ -224,7 +225,10 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * (no variant 1 of passes 0, 1, 3, 4, no z variant 2); for them "pass" 5 sets the
  * number of split-bf16 product terms per DFT-16: 6 (three pieces per
  * operand, all piece products of order <= 2; the default) or 3 (two pieces,
- * order <= 1). */
+ * order <= 1).  "Pass" 6 sets the z pass's tile, for every precision and
+ * for boxes: 0 = 16 pencils per workgroup in float, 8 in double (128-byte
+ * rows of the z pass's output), 1 = half as many (64-byte rows, half the LDS
+ * per workgroup, so that two or more workgroups share a compute unit). */
 ps_status ps_plan_set_variant(ps_plan p, int pass, int variant);
 
 /* Cells of spacings dx (the plan's), dy, dz along x, y, z instead of cubes
@@ -241,7 +245,8 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant);
 ps_status ps_plan_set_spacing(ps_plan p, double dy, double dz);
 
 /* Time every variant of every pass of a built pruned plan on its own
- * workspace (contents are overwritten), keep the fastest per pass and, if
+ * workspace (contents are overwritten; the z pass at both tile widths),
+ * keep the fastest per pass and, if
  * cache_path is not NULL, record the choice there for ps_plan_create (a text
  * file, one line per length and precision).  Synchronises `stream`; not
  * under stream capture. */

@@ -8,7 +8,8 @@ namespace ps {
 
 template <typename T> struct PrunedShape {
     static constexpr int ZT = sizeof(T) == 4 ? 16 : 8;  // y-pass tile: 128-byte rows of interleaved pencils
-    static constexpr int ZB = ZT;                       // z pass: rows of interleaved pencils too
+    static constexpr int ZB = ZT;                       // z pass: rows of interleaved pencils too (variant
+                                                        // ztile 1 halves it: 64-byte rows, half the LDS)
 };
 
 // Threads of a workgroup whose B pencils are each owned by one wavefront
@@ -22,9 +23,8 @@ constexpr int wave_threads(int B, int P, int E)
 
 // Whether the persistent z pass (EL elements per lane) fits the 160 KB of LDS
 // a workgroup can hold: its pencil buffer plus the copy of the column twiddles.
-template <typename T, int P, int FAM, int EL, int MT> constexpr bool z_pf_fits()
+template <typename T, int P, int FAM, int EL, int MT, int B = PrunedShape<T>::ZB> constexpr bool z_pf_fits()
 {
-    constexpr int B = PrunedShape<T>::ZB;
     using TL = TileZConv<T, P, FAM, B, wave_threads(B, P, EL), true, MT>;
     using RF = typename PlanFor<P, FAM>::Fwd;
     using RI = typename PlanFor<P, FAM>::Inv;
@@ -67,22 +67,23 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
         hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((N + ZT - 1) / ZT, H, b.count), dim3(NTY),
                            0, b.stream, static_cast<const V*>(b.in[1]), static_cast<V*>(b.out[1]), b.list, b.stab);
     }
-    template <bool WAVE> static void z_conv(const PrunedBufs& b)
+    // z pass: B pencils per workgroup (the full tile ZB or half of it)
+    template <bool WAVE, int B = ZB> static void z_conv(const PrunedBufs& b)
     {
-        constexpr int NTZ = WAVE ? wave_threads(ZB, P, EZ) : threads_for(ZB, P, EZ);
-        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT>), dim3(P / ZB, H, b.count), dim3(NTZ), 0, b.stream,
+        constexpr int NTZ = WAVE ? wave_threads(B, P, EZ) : threads_for(B, P, EZ);
+        hipLaunchKernelGGL((k_z_conv<T, P, FAM, B, NTZ, WAVE, MT>), dim3(P / B, H, b.count), dim3(NTZ), 0, b.stream,
                            static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab);
     }
     // Persistent passes: as many workgroups as fit on the device at once (a
     // multiple of 8, so z tile pairs stay on one XCD), each walking tiles.
     // EL: elements per lane that set the pencils per wavefront (32: two or
     // more 1024-point pencils per wavefront, 16: one).
-    template <int EL> static void z_conv_pf(const PrunedBufs& b)
+    template <int EL, int B = ZB> static void z_conv_pf(const PrunedBufs& b)
     {
-        constexpr int NTZ = wave_threads(ZB, P, EL);
-        static const int resident = resident_workgroups(k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>, NTZ);
-        const int total = (P / ZB) * H * b.count;
-        hipLaunchKernelGGL((k_z_conv_pf<T, P, FAM, ZB, NTZ, MT>), dim3(total < resident ? total : resident),
+        constexpr int NTZ = wave_threads(B, P, EL);
+        static const int resident = resident_workgroups(k_z_conv_pf<T, P, FAM, B, NTZ, MT>, NTZ);
+        const int total = (P / B) * H * b.count;
+        hipLaunchKernelGGL((k_z_conv_pf<T, P, FAM, B, NTZ, MT>), dim3(total < resident ? total : resident),
                            dim3(NTZ), 0, b.stream, static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list,
                            b.stab, b.count);
     }
@@ -128,10 +129,10 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
                            dim3((b.nz + ZT - 1) / ZT, b.nx + 1, b.count), dim3(NTY), 0, b.stream,
                            static_cast<const V*>(b.in[1]), static_cast<V*>(b.out[1]), b.list, b.stab);
     }
-    template <bool WAVE> static void z_conv_box(const PrunedBufs& b)
+    template <bool WAVE, int B = ZB> static void z_conv_box(const PrunedBufs& b)
     {
-        constexpr int NTZ = WAVE ? wave_threads(ZB, P, EZ) : threads_for(ZB, P, EZ);
-        hipLaunchKernelGGL((k_z_conv<T, P, FAM, ZB, NTZ, WAVE, MT, true>), dim3(2 * b.ny / ZB, b.nx + 1, b.count),
+        constexpr int NTZ = WAVE ? wave_threads(B, P, EZ) : threads_for(B, P, EZ);
+        hipLaunchKernelGGL((k_z_conv<T, P, FAM, B, NTZ, WAVE, MT, true>), dim3(2 * b.ny / B, b.nx + 1, b.count),
                            dim3(NTZ), 0, b.stream, static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list,
                            b.stab);
     }
@@ -148,6 +149,17 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
                            b.stab);
     }
 };
+
+// The z pass of a box with B pencils per workgroup.
+template <typename T, int P, int MT, int B> static void box_z(int zmode, const PrunedBufs& b)
+{
+    using L0 = PassLaunch<T, P, 0, MT>;
+    constexpr bool F1 = has_fam1<P>() && MT == 0;
+    using L1 = PassLaunch<T, P, F1 ? 1 : 0, MT>;
+    if (zmode == 2 && F1) L1::template z_conv_box<true, B>(b);
+    else if (zmode >= 1) L0::template z_conv_box<true, B>(b);
+    else L0::template z_conv_box<false, B>(b);
+}
 
 // One pass of a box solve with P its axis's length.  Boxes run the
 // one-tile-per-workgroup kernels (persistent variants are for cubes).
@@ -169,9 +181,8 @@ template <typename T, int P, int MT> static hipError_t box_pass(int pass, const 
         break;
     case 2:
         if (v.zmode >= 3) return hipErrorInvalidValue;
-        if (v.zmode == 2 && F1) L1::template z_conv_box<true>(b);
-        else if (v.zmode >= 1) L0::template z_conv_box<true>(b);
-        else L0::template z_conv_box<false>(b);
+        if (v.ztile == 1) box_z<T, P, MT, PrunedShape<T>::ZB / 2>(v.zmode, b);
+        else box_z<T, P, MT, PrunedShape<T>::ZB>(v.zmode, b);
         break;
     case 3:
         if (v.yi_fam & 2) return hipErrorInvalidValue;
@@ -186,6 +197,30 @@ template <typename T, int P, int MT> static hipError_t box_pass(int pass, const 
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// The fused z pass of a cube with B pencils per workgroup, in form zmode.
+template <typename T, int P, int MT, int B> static void cube_z(int zmode, const PrunedBufs& b)
+{
+    using L0 = PassLaunch<T, P, 0, MT>;
+    constexpr bool F1 = has_fam1<P>() && MT == 0;
+    using L1 = PassLaunch<T, P, F1 ? 1 : 0, MT>;
+    // (a persistent form that does not fit in LDS runs as the wave-owned pass)
+    if constexpr (PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1 && z_pf_fits<T, P, F1 ? 1 : 0, 32, MT, B>()) {
+        if (zmode == 3) {  // persistent: radix-32 family where it exists
+            L1::template z_conv_pf<32, B>(b);
+            return;
+        }
+    }
+    if constexpr (PlanFor<P, 0>::Fwd::S > 1 && z_pf_fits<T, P, 0, 16, MT, B>()) {
+        if (zmode == 4) {  // persistent: radix-16 family, one 1024-point pencil per wavefront
+            L0::template z_conv_pf<16, B>(b);
+            return;
+        }
+    }
+    if (zmode >= 2 && F1) L1::template z_conv<true, B>(b);
+    else if (zmode >= 1) L0::template z_conv<true, B>(b);
+    else L0::template z_conv<false, B>(b);
 }
 
 // Split matrix-core plans keep the radix-16 family (family 1 has no radix-16 stage).
@@ -206,22 +241,8 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else (v.y_fam & 2) ? L0::y_fwd_pf(b) : L0::y_fwd(b);
             break;
         case 2:
-            // (a persistent form that does not fit in LDS runs as the wave-owned pass)
-            if constexpr (PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1 && z_pf_fits<T, P, F1 ? 1 : 0, 32, MT>()) {
-                if (v.zmode == 3) {  // persistent: radix-32 family where it exists
-                    L1::template z_conv_pf<32>(b);
-                    break;
-                }
-            }
-            if constexpr (PlanFor<P, 0>::Fwd::S > 1 && z_pf_fits<T, P, 0, 16, MT>()) {
-                if (v.zmode == 4) {  // persistent: radix-16 family, one 1024-point pencil per wavefront
-                    L0::template z_conv_pf<16>(b);
-                    break;
-                }
-            }
-            if (v.zmode >= 2 && F1) L1::template z_conv<true>(b);
-            else if (v.zmode >= 1) L0::template z_conv<true>(b);
-            else L0::template z_conv<false>(b);
+            if (v.ztile == 1) cube_z<T, P, MT, PrunedShape<T>::ZB / 2>(v.zmode, b);
+            else cube_z<T, P, MT, PrunedShape<T>::ZB>(v.zmode, b);
             break;
         case 3:
             if ((v.yi_fam & 1) && F1) (v.yi_fam & 2) ? L1::y_inv_pf(b) : L1::y_inv(b);

@@ -351,10 +351,10 @@ const char* prec_name(ps_precision p)
     return "?";
 }
 
-int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 4 : 2; }
+int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 4 : 2; }  // pass 6 (z tile): 2
 
 // Whether variant v of a pass runs the radix-32-based plan family.
-bool variant_needs_family1(int pass, int v) { return pass == 2 ? v == 2 : (v & 1) != 0; }
+bool variant_needs_family1(int pass, int v) { return pass == 6 ? false : pass == 2 ? v == 2 : (v & 1) != 0; }
 // Whether the axis a pass transforms has the radix-32-based family.
 bool family1_available(ps_plan p, int pass)
 {
@@ -378,6 +378,7 @@ int* variant_slot(ps::PrunedVariant& v, int pass)
     case 1: return &v.y_fam;
     case 2: return &v.zmode;
     case 3: return &v.yi_fam;
+    case 6: return &v.ztile;
     default: return &v.xc_fam;
     }
 }
@@ -393,9 +394,66 @@ bool variant_ok(ps_plan p, int pass, int variant)
     return true;
 }
 
-// Tuning cache: one line per (P, precision): "P prec x y z yi xc".  A line
-// whose variants this plan cannot run is ignored; the split product-term
-// count (not part of the line) is kept.
+// Default z pass per padded length: the fastest form (variant 0..4) and
+// tile width (0: full, 1: half) measured on MI355X for FP64, FP32 and
+// FP32-split.  P = 64, 96, 128, 192, 256 (the lengths of batches of uneven
+// small solves): the wave-owned form on the full tile, the fastest for the
+// 96-solve batch as a whole (groups run side by side on forked streams,
+// where persistent forms, which fill the device, and the half tile measured
+// 1-8% slower), though not always for one solve alone.  Other lengths: the
+// pass timed alone on one cube of P/2 cells, each form at both widths; a
+// choice replaced the earlier rule only where it was at least 3% faster.
+struct ZDefault {
+    int P;
+    signed char zmode[3], ztile[3];  // [FP64, FP32, FP32-split]
+};
+const ZDefault Z_DEFAULTS[] = {
+    {  16, {1, 3, 1}, {0, 1, 0}},
+    {  32, {1, 1, 1}, {0, 0, 0}},
+    {  48, {1, 1, 0}, {0, 0, 1}},
+    {  64, {1, 1, 1}, {0, 0, 0}},
+    {  80, {1, 1, 0}, {0, 0, 1}},
+    {  96, {1, 1, 1}, {0, 0, 0}},
+    { 128, {1, 1, 1}, {0, 0, 0}},
+    { 144, {1, 1, 1}, {1, 0, 0}},
+    { 160, {1, 0, 0}, {0, 1, 0}},
+    { 192, {1, 1, 1}, {0, 0, 0}},
+    { 240, {1, 1, 4}, {1, 1, 1}},
+    { 256, {1, 1, 1}, {0, 0, 0}},
+    { 288, {0, 0, 1}, {0, 1, 1}},
+    { 320, {0, 0, 0}, {0, 1, 1}},
+    { 384, {0, 0, 0}, {0, 1, 1}},
+    { 400, {4, 4, 1}, {0, 1, 0}},
+    { 432, {1, 1, 1}, {0, 0, 0}},
+    { 480, {1, 1, 1}, {0, 0, 1}},
+    { 512, {4, 3, 4}, {0, 0, 1}},
+    { 576, {1, 1, 1}, {0, 0, 0}},
+    { 640, {1, 3, 1}, {1, 1, 1}},
+    { 720, {0, 1, 1}, {1, 0, 0}},
+    { 768, {0, 0, 1}, {1, 1, 1}},
+    { 800, {4, 1, 1}, {0, 0, 0}},
+    { 864, {1, 4, 1}, {0, 1, 0}},
+    { 960, {1, 1, 1}, {0, 0, 0}},
+    {1024, {2, 3, 1}, {1, 0, 1}},
+};
+
+bool z_default(int P, ps_precision prec, int& zmode, int& ztile)
+{
+    const int k = prec == PS_F64 ? 0 : prec == PS_F32 ? 1 : prec == PS_F32_SPLIT ? 2 : -1;
+    if (k < 0) return false;
+    for (const ZDefault& d : Z_DEFAULTS)
+        if (d.P == P) {
+            zmode = d.zmode[k];
+            ztile = d.ztile[k];
+            return true;
+        }
+    return false;
+}
+
+// Tuning cache: one line per (P, precision): "P prec x y z yi xc zt" (zt,
+// the z-pass tile, may be absent: 0).  A line whose variants this plan
+// cannot run is ignored; the split product-term count (not part of the
+// line) is kept.
 bool read_tuning(const char* path, ps_plan p)
 {
     std::ifstream f(path);
@@ -406,13 +464,15 @@ bool read_tuning(const char* path, ps_plan p)
         std::istringstream is(line);
         int pp;
         std::string pr;
-        int v[5];
+        int v[5], zt = 0;
         if (!(is >> pp >> pr >> v[0] >> v[1] >> v[2] >> v[3] >> v[4])) continue;
+        if (!(is >> zt)) zt = 0;
         if (pp != p->P || pr != prec_name(p->prec)) continue;
-        bool ok = true;
+        bool ok = zt == 0 || zt == 1;
         for (int k = 0; k < 5; ++k) ok = ok && variant_ok(p, k, v[k]);
         if (!ok) continue;
         for (int k = 0; k < 5; ++k) *variant_slot(p->var, k) = v[k];  // the last valid matching line wins
+        p->var.ztile = zt;
         found = true;
     }
     return found;
@@ -436,7 +496,7 @@ bool write_tuning(const char* path, int P, ps_precision prec, const ps::PrunedVa
     if (!o) return false;
     for (auto& l : keep) o << l << "\n";
     o << P << " " << prec_name(prec) << " " << v.x_fam << " " << v.y_fam << " " << v.zmode << " " << v.yi_fam << " "
-      << v.xc_fam << "\n";
+      << v.xc_fam << " " << v.ztile << "\n";
     return (bool)o;
 }
 
@@ -540,19 +600,18 @@ ps_status create_plan(ps_plan* out, int nx, int ny, int nz, double dx, double dy
         p->tables.resize(p->split_tab + st.size() * sizeof(unsigned short), 0);
         std::memcpy(p->tables.data() + p->split_tab, st.data(), st.size() * sizeof(unsigned short));
     }
-    // Default variants, as measured fastest per pass on MI355X: wave-owned
-    // z pass; where the radix-32-based family exists (P = 512, 1024) it wins
-    // for the forward y pass and, in FP32, the z pass (its persistent,
-    // prefetching form), while the x passes keep the radix-16-based family
-    // (except FP64 at P = 1024, whose forward x pass is faster on radix 32);
-    // at P = 1024 the inverse y pass runs persistent (radix-32 family in
-    // FP32, radix-16 in FP64).  Split plans keep the radix-16 stages (their
-    // matrix-core DFT-16) and the wave-owned z pass, except at P = 768,
-    // where the workgroup-synchronised one is faster.  Boxes take the
+    // Default variants, as measured fastest per pass on MI355X: where the
+    // radix-32-based family exists (P = 512, 1024) it wins for the forward y
+    // pass, while the x passes keep the radix-16-based family (except FP64
+    // at P = 1024, whose forward x pass is faster on radix 32); at P = 1024
+    // the inverse y pass runs persistent (radix-32 family in FP32, radix-16
+    // in FP64).  Split plans keep the radix-16 stages (their matrix-core
+    // DFT-16).  The z pass's form and tile width come from the measured
+    // table Z_DEFAULTS (the rules below are its fallback).  Boxes take the
     // one-tile-per-workgroup forms, per axis length.
     const int Py = axis_pad(p, 1), Pz = axis_pad(p, 2);
     if (prec == PS_F32_SPLIT) {
-        p->var.zmode = Pz == 768 ? 0 : 1;
+        p->var.zmode = 1;
         p->var.mterms = 6;
     } else if (box) {
         p->var.y_fam = ps::has_family1(Py) ? 1 : 0;
@@ -564,6 +623,15 @@ ps_status create_plan(ps_plan* out, int nx, int ny, int nz, double dx, double dy
         if (p->P >= 1024 && prec == PS_F64) p->var.x_fam = 1;
     } else {
         p->var.zmode = 1;
+    }
+    // the z pass's form and tile width per length, as measured (boxes take
+    // the one-tile-per-workgroup forms only)
+    if (!is_plain(prec)) {
+        int zm = 0, zt = 0;
+        if (z_default(Pz, prec, zm, zt) && (!box || zm <= 2)) {
+            p->var.zmode = zm;
+            p->var.ztile = zt;
+        }
     }
     if (tune_cache && !is_plain(prec) && !box) read_tuning(tune_cache, p);
     const size_t Ny = ny, Nz = nz, Hx = nx + 1, Hy = ny + 1, Hz = nz + 1;
@@ -653,6 +721,7 @@ ps_status ps_plan_query(ps_plan p, ps_plan_info* info)
         info->t3_offset = p->off_t3;
         for (int k = 0; k < 5; ++k) info->variant[k] = *variant_slot(p->var, k);
         info->split_terms = p->var.mterms;
+        info->z_tile = p->var.ztile;
     }
     return PS_OK;
 }
@@ -871,7 +940,12 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
         p->var.mterms = variant;
         return PS_OK;
     }
-    if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..5");
+    if (pass == 6) {
+        if (variant != 0 && variant != 1) return fail(PS_ERR_INVALID, "z tile must be 0 (full) or 1 (half)");
+        p->var.ztile = variant;
+        return PS_OK;
+    }
+    if (pass < 0 || pass > 4) return fail(PS_ERR_INVALID, "pass must be 0..6");
     if (variant < 0 || variant >= num_variants(pass)) return fail(PS_ERR_INVALID, "variant out of range");
     if (variant_needs_family1(pass, variant) && !family1_available(p, pass))
         return fail(PS_ERR_UNSUPPORTED, "this plan has no radix-32 plan family");
@@ -915,9 +989,12 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
     ps::PrunedVariant best = p->var;
     for (int pass = 0; pass < 5 && rc == PS_OK; ++pass) {
         float best_ms = 1e30f;
-        for (int v = 0; v < num_variants(pass); ++v) {
+        // the z pass: every form at both tile widths
+        for (int vt = 0; vt < num_variants(pass) * (pass == 2 ? 2 : 1); ++vt) {
+            const int v = vt % num_variants(pass);
             if (!variant_ok(p, pass, v)) continue;
             *variant_slot(b.var, pass) = v;
+            if (pass == 2) b.var.ztile = vt / num_variants(pass);
             const int reps = 5;
             float ms = 0.f;
             for (int r = 0; r <= reps && rc == PS_OK; ++r) {
@@ -933,9 +1010,11 @@ ps_status ps_autotune(ps_plan p, void* stream, const char* cache_path)
             if (rc == PS_OK && ms < best_ms) {
                 best_ms = ms;
                 *variant_slot(best, pass) = v;
+                if (pass == 2) best.ztile = b.var.ztile;
             }
         }
         *variant_slot(b.var, pass) = *variant_slot(best, pass);
+        if (pass == 2) b.var.ztile = best.ztile;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -985,8 +1064,8 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
     // same kernel is one launch over their adjacent records.
     auto vkey = [&](int i) {
         const ps::PrunedVariant& v = plans[i]->var;
-        return std::array<int, 10>{-plans[i]->nx * plans[i]->ny * plans[i]->nz, -plans[i]->nz, -plans[i]->ny,
-                                  -plans[i]->nx, v.x_fam, v.y_fam, v.zmode, v.yi_fam, v.xc_fam, v.mterms};
+        return std::array<int, 11>{-plans[i]->nx * plans[i]->ny * plans[i]->nz, -plans[i]->nz, -plans[i]->ny,
+                                  -plans[i]->nx, v.x_fam, v.y_fam, v.zmode, v.yi_fam, v.xc_fam, v.mterms, v.ztile};
     };
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -1013,7 +1092,8 @@ ps_status ps_solve_batched(const ps_plan* plans, int count, const void* const* d
                 ps::PrunedVariant v1 = plans[order[k1]]->var;
                 const ps_plan a = plans[order[k0]], c = plans[order[k1]];
                 if (c->nx != a->nx || c->ny != a->ny || c->nz != a->nz ||
-                    *variant_slot(v1, pass) != *variant_slot(v0, pass) || v1.mterms != v0.mterms)
+                    *variant_slot(v1, pass) != *variant_slot(v0, pass) || v1.mterms != v0.mterms ||
+                    (pass == 2 && v1.ztile != v0.ztile))
                     break;
                 ++k1;
             }

@@ -20,10 +20,13 @@ namespace ps {
 // 3 persistent wave-owned pencils with a one-tile prefetch (family 1 where
 // it exists, else family 0; split plans: family 0), 4 the same on family 0
 // with fewer pencils per wavefront (one at P = 1024).  Boxes take the
-// one-tile-per-workgroup variants only (y: 0, 1; z: 0, 1, 2).
+// one-tile-per-workgroup variants only (y: 0, 1; z: 0, 1, 2).  ztile: pencils
+// per z-pass workgroup, 0 the full tile (16 float, 8 double: 128-byte output
+// rows), 1 half of it (64-byte rows, half the LDS, twice the workgroups).
 struct PrunedVariant {
     int x_fam = 0, y_fam = 0, zmode = 0, yi_fam = 0, xc_fam = 0;
     int mterms = 0;  // 0: vector-ALU DFTs; 3 or 6: split-bf16 matrix-core radix-16 DFTs (float only)
+    int ztile = 0;
 };
 constexpr int NUM_ZMODES = 5;
 

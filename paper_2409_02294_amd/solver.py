@@ -58,7 +58,7 @@ class PlanInfo(ctypes.Structure):
                 ("t1_offset", ctypes.c_size_t), ("t2_offset", ctypes.c_size_t), ("t3_offset", ctypes.c_size_t),
                 ("variant", ctypes.c_int * 5),
                 ("split_terms", ctypes.c_int), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
-                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int)]
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("z_tile", ctypes.c_int)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -148,7 +148,7 @@ def ps_plan_query(plan: int) -> Dict:
     return dict(n=info.n, p=info.p, h=info.h, precision=info.precision, dx=info.dx,
                 workspace_bytes=info.workspace_bytes, ghat_bytes=info.ghat_bytes, ready=bool(info.ready),
                 radices=rad, t1_offset=info.t1_offset, t2_offset=info.t2_offset, t3_offset=info.t3_offset, variant=list(info.variant), split_terms=info.split_terms,
-                dy=info.dy, dz=info.dz, nx=info.nx, ny=info.ny, nz=info.nz)
+                dy=info.dy, dz=info.dz, nx=info.nx, ny=info.ny, nz=info.nz, z_tile=info.z_tile)
 
 
 def ps_green_build(plan: int, workspace: int, G: float, self_coeff: float, stream: int) -> None:

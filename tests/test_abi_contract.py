@@ -152,7 +152,11 @@ def test_variant_selection_contract():
     q = S.ps_plan_create(256, 1.0 / 256, S.PS_F64)
     try:
         lib = S.load()
-        assert lib.ps_plan_set_variant(p, 6, 0) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 7, 0) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 6, 2) == S.PS_ERR_INVALID     # z tile: 0 (full) or 1 (half)
+        assert lib.ps_plan_set_variant(p, 6, 1) == S.PS_OK
+        assert S.ps_plan_query(p)["z_tile"] == 1
+        assert lib.ps_plan_set_variant(q, 6, 1) == S.PS_OK
         assert lib.ps_plan_set_variant(p, 5, 6) == S.PS_ERR_UNSUPPORTED  # product terms: split plans only
         assert lib.ps_plan_set_variant(p, 2, 5) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
@@ -192,10 +196,17 @@ def test_spacing_contract():
 
 def test_tuning_cache_is_read(tmp_path):
     path = tmp_path / "tune.txt"
-    path.write_text("64 f32 0 0 0 0 0\n512 f32 0 1 1 0 1\n512 f64 1 1 2 1 1\n")
+    path.write_text("64 f32 0 0 0 0 0\n512 f32 0 1 1 0 1\n512 f64 1 1 2 1 1 1\n")
     p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32, str(path))
     try:
-        assert S.ps_plan_query(p)["variant"] == [0, 1, 1, 0, 1]
+        info = S.ps_plan_query(p)
+        assert info["variant"] == [0, 1, 1, 0, 1] and info["z_tile"] == 0  # a line without the z tile: 0
+    finally:
+        S.ps_plan_destroy(p)
+    p = S.ps_plan_create(256, 1.0 / 256, S.PS_F64, str(path))
+    try:
+        info = S.ps_plan_query(p)
+        assert info["variant"] == [1, 1, 2, 1, 1] and info["z_tile"] == 1
     finally:
         S.ps_plan_destroy(p)
     # a missing file keeps the defaults (radix-32 family for the forward y pass
@@ -219,12 +230,15 @@ def test_tuning_cache_is_read(tmp_path):
         assert S.ps_plan_query(p)["variant"] == [0, 0, 1, 0, 0]  # zmode 9 does not exist: defaults kept
     finally:
         S.ps_plan_destroy(p)
-    for n, prec, want in [(512, S.PS_F32, [0, 1, 3, 3, 0]), (512, S.PS_F64, [1, 1, 1, 2, 0]),
-                          (256, S.PS_F64, [0, 1, 2, 0, 0]), (384, S.PS_F32_SPLIT, [0, 0, 0, 0, 0]),
-                          (128, S.PS_F32, [0, 0, 1, 0, 0]), (512, S.PS_F32_SPLIT, [0, 0, 1, 0, 0])]:
+    # measured defaults: variants and z tile
+    for n, prec, want, zt in [(512, S.PS_F32, [0, 1, 3, 3, 0], 0), (512, S.PS_F64, [1, 1, 2, 2, 0], 1),
+                              (256, S.PS_F64, [0, 1, 4, 0, 0], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 0, 0], 1),
+                              (128, S.PS_F32, [0, 0, 1, 0, 0], 0), (512, S.PS_F32_SPLIT, [0, 0, 1, 0, 0], 1),
+                              (384, S.PS_F32, [0, 0, 0, 0, 0], 1), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
         try:
-            assert S.ps_plan_query(p)["variant"] == want, (n, prec)
+            info = S.ps_plan_query(p)
+            assert (info["variant"], info["z_tile"]) == (want, zt), (n, prec)
         finally:
             S.ps_plan_destroy(p)
 
@@ -234,7 +248,7 @@ def test_split_plan_contract():
     try:
         info = S.ps_plan_query(p)
         assert info["split_terms"] == 6
-        assert info["variant"] == [0, 0, 1, 0, 0]
+        assert info["variant"] == [0, 0, 4, 0, 0] and info["z_tile"] == 1
         lib = S.load()
         assert lib.ps_plan_set_variant(p, 5, 4) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # keeps the radix-16 family

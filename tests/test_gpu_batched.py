@@ -91,6 +91,11 @@ def test_batch_mixed_variants(prec):
     if prec == "f32_split":  # product terms differ per plan too
         S.ps_plan_set_variant(solvers[1].plan, 5, 3)
         S.ps_plan_set_variant(solvers[5].plan, 5, 3)
+    # and z tiles: members 3 and 4 share every pass variant but the z tile
+    v3 = solvers[3].info()
+    for k in range(5):
+        S.ps_plan_set_variant(solvers[4].plan, k, v3["variant"][k])
+    S.ps_plan_set_variant(solvers[4].plan, 6, 1 - v3["z_tile"])
     eager = [s(r) for s, r in zip(solvers, rhos)]
     outs = S.solve_batched(solvers, rhos)
     torch.cuda.synchronize()

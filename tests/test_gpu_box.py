@@ -154,7 +154,7 @@ def test_box_variants_agree(prec):
     s = S.Solver(dims, 1.0 / 256, prec)
     ref = s(rho).double()
     tol = 1e-13 if prec == "f64" else 1e-6
-    for pass_id, variants in ((0, (0, 1)), (1, (0, 1)), (2, (0, 1)), (3, (0, 1)), (4, (0, 1))):
+    for pass_id, variants in ((0, (0, 1)), (1, (0, 1)), (2, (0, 1)), (3, (0, 1)), (4, (0, 1)), (6, (0, 1))):
         for v in variants:
             t = S.Solver(dims, 1.0 / 256, prec)
             S.ps_plan_set_variant(t.plan, pass_id, v)

@@ -348,15 +348,40 @@ def test_variants_agree_n256(prec):
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 @pytest.mark.parametrize("n", [16, 48, 96, 120])
 @pytest.mark.parametrize("zmode", [0, 1, 3, 4])
-def test_zmodes_match_oracle(prec, n, zmode):
+@pytest.mark.parametrize("ztile", [0, 1])
+def test_zmodes_match_oracle(prec, n, zmode, ztile):
     rho = inputs.make_density(n, 5, 500 + n, sigma=(0.03, 0.1), noise=1e-3)
     s = S.Solver(n, 1.0 / n, prec)
     S.ps_plan_set_variant(s.plan, 2, zmode)
+    S.ps_plan_set_variant(s.plan, 6, ztile)
     r = torch.from_numpy(rho).to("cuda", _dtype(prec))
     got = s(r).double().cpu().numpy()
     ref = oracle.fft_conv(r.double().cpu().numpy(), 1.0 / n)
-    l2, _ = _report(f"zmode {zmode} n={n} {prec}", got, ref)
+    l2, _ = _report(f"zmode {zmode} ztile {ztile} n={n} {prec}", got, ref)
     assert l2 <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
+@pytest.mark.parametrize("n", [40, 128, 192, 384])
+def test_z_tile_widths_agree(prec, n):
+    # a pencil's arithmetic does not depend on how many pencils share a
+    # workgroup: both tile widths agree to rounding in every z form (not
+    # always bitwise: the compiler may contract products into FMAs
+    # differently in the two kernels)
+    rho = inputs.make_density(n, 6, 900 + n, sigma=(0.03, 0.08), noise=1e-3)
+    s = S.Solver(n, 1.0 / n, prec)
+    r = torch.from_numpy(rho).to("cuda", _dtype(prec))
+    for zmode in range(5):
+        try:
+            S.ps_plan_set_variant(s.plan, 2, zmode)
+        except S.PSError:
+            continue
+        S.ps_plan_set_variant(s.plan, 6, 0)
+        a = s(r).double()
+        S.ps_plan_set_variant(s.plan, 6, 1)
+        b = s(r).double()
+        err = float((a - b).norm() / a.norm())
+        assert err <= (1e-14 if prec == "f64" else 2e-7), (zmode, n, prec, err)
 
 
 def test_persistent_z_fallback_where_lds_is_short():
@@ -380,9 +405,10 @@ def test_autotune_writes_cache(tmp_path):
     S.ps_autotune(s.plan, torch.cuda.current_stream().cuda_stream, path)
     lines = open(path).read().split()
     assert lines[:2] == ["128", "f32"]
-    chosen = s.info()["variant"]
+    chosen = s.info()["variant"], s.info()["z_tile"]
     s2 = S.Solver(n, 1.0 / n, "f32", tune_cache=path)
-    assert s2.info()["variant"] == chosen
+    assert (s2.info()["variant"], s2.info()["z_tile"]) == chosen
+    assert len(open(path).read().split()) == 8  # P, precision, five variants, the z tile
     rho = inputs.make_density(n, 5, 7, sigma=(0.03, 0.1))
     r = torch.from_numpy(rho).to("cuda", torch.float32)
     got = s2(r).double().cpu().numpy()
