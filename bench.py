@@ -71,7 +71,8 @@ def model_bytes(n: int, rb: int):
 # host layer, the kernel-spectrum build and the plain method do not change
 # what those kernels read and write).
 PASS_KERNEL_SOURCES = ("fft_engine.hpp", "k_pruned.hpp", "launch_pruned.hpp", "launch_pruned_f32.hip",
-                       "launch_pruned_f64.hip", "launch_pruned_split.hip", "plans.hpp", "ps_complex.hpp",
+                       "launch_pruned_f64.hip", "launch_pruned_split6.hip", "launch_pruned_split3.hip", "plans.hpp",
+                       "ps_complex.hpp",
                        "ps_internal.hpp", "solve_rec.hpp")
 
 
@@ -86,9 +87,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n: int, prec: str, variant: int):
+def measured_traffic(kernel: str, n: int, prec: str, variant: int, z_tile: int = 0):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources with the same kernel variant; else None."""
+    taken on the current kernel sources with the same kernel variant (and, for
+    the z pass, tile width); else None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -97,6 +99,8 @@ def measured_traffic(kernel: str, n: int, prec: str, variant: int):
             d = json.load(fh)
         rec = d["kernels"][f"{kernel}/n{n}/{prec}"]
         if rec.get("source_hash") != source_hash() or rec.get("variant") != variant:
+            return None
+        if kernel == "z_conv" and rec.get("z_tile", 0) != z_tile:
             return None
         return float(rec["bytes_per_launch"])
     except Exception:
@@ -576,6 +580,8 @@ def pass_loop(torch, S, args) -> int:
     if args.variants:
         for k, v in enumerate(int(x) for x in args.variants.split(",")):
             S.ps_plan_set_variant(s.plan, k, v)
+    if args.z_tile >= 0:
+        S.ps_plan_set_variant(s.plan, 6, args.z_tile)
     info = s.info()
     ws = s.workspace.data_ptr()
     t1, t2, t3 = ws + info["t1_offset"], ws + info["t2_offset"], ws + info["t3_offset"]
@@ -630,13 +636,15 @@ def ingest_counters(args) -> int:
     fac = {w: copy_kib / avg[w]["copy"] for w in ("fetch", "write")}
     rb = 8 if args.precision.startswith("f64") else 4
     pb = pass_bytes(args.n, rb)
+    # the library defaults (plan creation makes no HIP call), or the variants given
+    from paper_2409_02294_amd import solver as S
+    plan = S.ps_plan_create(args.n, 1.0 / args.n, S.PRECISIONS[args.precision], None)
+    variants, z_tile = S.ps_plan_query(plan)["variant"], S.ps_plan_query(plan)["z_tile"]
+    S.ps_plan_destroy(plan)
     if args.variants:
         variants = [int(x) for x in args.variants.split(",")]
-    else:  # the library defaults (plan creation makes no HIP call)
-        from paper_2409_02294_amd import solver as S
-        plan = S.ps_plan_create(args.n, 1.0 / args.n, S.PRECISIONS[args.precision], None)
-        variants = S.ps_plan_query(plan)["variant"]
-        S.ps_plan_destroy(plan)
+    if args.z_tile >= 0:
+        z_tile = args.z_tile
     out_path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.json")
     doc = {"about": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each "
                     "scaled by the factor that makes a 1 GiB elementwise copy read and write 1 GiB",
@@ -655,6 +663,8 @@ def ingest_counters(args) -> int:
             "algorithmic_bytes": pb[k], "ratio_to_algorithmic": (f + w) * 1024.0 / pb[k],
             "variant": variants[PASS_NAMES.index(k)], "source_hash": source_hash(),
         }
+        if k == "z_conv":
+            doc["kernels"][f"{k}/n{args.n}/{args.precision}"]["z_tile"] = z_tile
     with open(out_path, "w") as fh:
         json.dump(doc, fh, indent=1)
     print(json.dumps(doc["kernels"], indent=1))
@@ -679,6 +689,8 @@ def main() -> int:
                     help="instead of the benchmark: run each pass of one solve K times, then a 1 GiB "
                          "elementwise copy K times (the target of the HBM counter runs)")
     ap.add_argument("--variants", default="", help="kernel variants per pass for --pass-loop, e.g. 0,1,2,0,0")
+    ap.add_argument("--z-tile", type=int, default=-1, help="z-pass tile width for --pass-loop (0 full, 1 half; "
+                                                             "default: the plan's)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs of a --pass-loop run into "
                          "profiles/hbm_traffic_counters.json")
@@ -747,6 +759,7 @@ def main() -> int:
             rec["label"] = "split-bf16 with three product terms: reported, does not meet the 1e-6 bound"
         if not prec.endswith("plain"):
             rec["variants"] = s.info()["variant"]
+            rec["z_tile"] = s.info()["z_tile"]
             pms = time_passes(torch, S, s, rho, phi, max(3, steps // 2))
             pb = pass_bytes(n, 8 if prec.startswith("f64") else 4)
             rec["pass_ms"] = dict(zip(PASS_NAMES, pms))
@@ -808,7 +821,7 @@ def main() -> int:
         ach = pb[kname] / (pass_ms[dom] * 1e-3) / 1e9
         out["pass_ms"] = hr["pass_ms"]
         out["pass_GBps"] = hr["pass_GBps"]
-        traffic = measured_traffic(kname, n, head, hr["variants"][dom])
+        traffic = measured_traffic(kname, n, head, hr["variants"][dom], hr.get("z_tile", 0))
         out["roofline"] = {
             "kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBS, "traffic": traffic,

@@ -76,11 +76,12 @@ __device__ __forceinline__ void block_copy(SRC&& src, DST&& dst)
 }
 
 // ---------------------------------------------------------------------------
-// x_r2c: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
+// x_r2c: ROWS rows (ROWS/2 packed pairs) of one z-plane; tile (y-tile bx, z by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false> struct TileXR2C {
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false, int ROWS = 16> struct TileXR2C {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, 8, NT, false, MT>;
+    static_assert(ROWS == 8 || ROWS == 16 || ROWS == 32, "rows per x tile");
+    using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ROWS / 2, NT, false, MT>;
     static constexpr int N = P / 2, H = N + 1;  // x length, half spectrum
     static constexpr int LDS = E::LDS_ELEMS;
     __device__ __forceinline__ static void run(int bx, int by, const T* __restrict__ rho, V* __restrict__ t1,
@@ -88,7 +89,7 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = fa
                                                int ny_box = 0, int nz_box = 0)
     {
         const int Ny = ext<BOX>(ny_box, N), Nz = ext<BOX>(nz_box, N);
-        const int y0 = bx * 16;
+        const int y0 = bx * ROWS;
         const int z = by;
         const T* plane = rho + ((size_t)z * Ny + y0) * N;  // block-uniform base, 32-bit offsets below
         auto ld = [&](int p, int idx) -> V {
@@ -102,9 +103,9 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = fa
         __syncthreads();
         V* t1z = t1 + (size_t)z * Ny;
         // separate the two half spectra of each packed pair: element e is
-        // (row e % 16, k = e / 16), written to T1[k][z][y0 + row]
+        // (row e % ROWS, k = e / ROWS), written to T1[k][z][y0 + row]
         auto sep = [&](int e) -> V {
-            const int row = e & 15, k = e >> 4;
+            const int row = (int)((unsigned)e % ROWS), k = (int)((unsigned)e / ROWS);
             const int p = row >> 1;
             const V z1 = lds[E::lidx(p, k)];
             const V z2 = lds[E::lidx(p, k == 0 ? 0 : P - k)];
@@ -112,10 +113,10 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = fa
             return V{T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
         };
         auto put = [&](int e, V x) {
-            const int row = e & 15, k = e >> 4;
+            const int row = (int)((unsigned)e % ROWS), k = (int)((unsigned)e / ROWS);
             if (y0 + row < Ny) t1z[(unsigned)(k * Nz * Ny + y0 + row)] = x;
         };
-        block_copy<V, NT, 16 * H>(sep, put);
+        block_copy<V, NT, ROWS * H>(sep, put);
     }
 };
 
@@ -223,21 +224,22 @@ template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool 
 // ---------------------------------------------------------------------------
 // x_c2r: 16 rows (8 packed pairs) of one z-plane; tile (y-tile bx, z by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false> struct TileXC2R {
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false, int ROWS = 16> struct TileXC2R {
     using V = cx<T>;
-    using E = Engine<T, typename PlanFor<P, FAM>::Inv, 8, NT, false, MT>;
+    static_assert(ROWS == 8 || ROWS == 16 || ROWS == 32, "rows per x tile");
+    using E = Engine<T, typename PlanFor<P, FAM>::Inv, ROWS / 2, NT, false, MT>;
     static constexpr int N = P / 2, H = N + 1, HP = t4_pitch(H);  // x length, half spectrum, T4 pitch
     static constexpr int XP = H + 1;  // pitch of the staged half spectra
-    static constexpr int LDS = E::LDS_ELEMS > 16 * XP ? E::LDS_ELEMS : 16 * XP;
+    static constexpr int LDS = E::LDS_ELEMS > ROWS * XP ? E::LDS_ELEMS : ROWS * XP;
     __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t4, T* __restrict__ phi,
                                                const V* __restrict__ tw, V* lds, const typename E::SA& sa,
                                                int ny_box = 0)
     {
         const int Ny = ext<BOX>(ny_box, N);
-        const int y0 = bx * 16;
+        const int y0 = bx * ROWS;
         const int z = by;
-        const V* rows = t4 + ((size_t)z * Ny + y0) * HP;  // 16 consecutive rows of H (pitch HP)
-        block_copy<V, NT, 16 * H>(
+        const V* rows = t4 + ((size_t)z * Ny + y0) * HP;  // ROWS consecutive rows of H (pitch HP)
+        block_copy<V, NT, ROWS * H>(
             [&](int e) -> V {
                 const int row = e / H, k = e - row * H;
                 return y0 + row < Ny ? rows[(unsigned)(row * HP + k)] : V{T(0), T(0)};
@@ -297,11 +299,11 @@ template <typename V, int FAM, int AX> __device__ __forceinline__ const V* tw_in
     return gp<const V>(FAM == 1 ? s.twi1[AX] : s.twi[AX]);
 }
 
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false>
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false, int ROWS = 16>
 __global__ __launch_bounds__(NT) void k_x_r2c(const T* in, cx<T>* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileXR2C<T, P, FAM, NT, MAP_MID, MT, BOX>;
+    using TL = TileXR2C<T, P, FAM, NT, MAP_MID, MT, BOX, ROWS>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
@@ -564,11 +566,11 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* in, cx<T>* out, const
             lds, sa, ext<BOX>(s.nx, 0), ext<BOX>(s.nz, 0));
 }
 
-template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false>
+template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = false, int ROWS = 16>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* in, T* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileXC2R<T, P, FAM, NT, MAP_MID, MT, BOX>;
+    using TL = TileXC2R<T, P, FAM, NT, MAP_MID, MT, BOX, ROWS>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;

@@ -32,6 +32,14 @@ template <typename T, int P, int FAM, int EL, int MT, int B = PrunedShape<T>::ZB
     return (TL::LDS + C) * (int)sizeof(cx<T>) <= 160 * 1024;
 }
 
+// Whether the x passes with ROWS rows per workgroup fit the LDS.
+template <typename T, int P, int FAM, int ROWS, int MT> constexpr bool x_fits()
+{
+    constexpr int NTR = threads_for(ROWS / 2, P, FAM == 1 ? 32 : 16);
+    return TileXR2C<T, P, FAM, NTR, MAP_EF, MT, false, ROWS>::LDS * (int)sizeof(cx<T>) <= 160 * 1024 &&
+           TileXC2R<T, P, FAM, NTR, MAP_EF, MT, false, ROWS>::LDS * (int)sizeof(cx<T>) <= 160 * 1024;
+}
+
 // Workgroups of `kernel` (nt threads) resident on the device at once, rounded
 // down to a multiple of 8 (the XCD count); a fallback if the query fails.
 template <class K> static int resident_workgroups(K kernel, int nt)
@@ -57,10 +65,13 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     static constexpr int NTX = threads_for(8, P, E);
     static constexpr int NTY = threads_for(ZT, P, E);
 
-    static void x_r2c(const PrunedBufs& b)
+    // x passes: ROWS rows of one z-plane per workgroup (ROWS / 2 packed pencils)
+    template <int ROWS = 16> static void x_r2c(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N, b.count), dim3(NTX), 0,
-                           b.stream, static_cast<const T*>(b.in[0]), static_cast<V*>(b.out[0]), b.list, b.stab);
+        constexpr int NTR = threads_for(ROWS / 2, P, E);
+        hipLaunchKernelGGL((k_x_r2c<T, P, FAM, NTR, MAP_EF, MT, false, ROWS>), dim3((N + ROWS - 1) / ROWS, N, b.count),
+                           dim3(NTR), 0, b.stream, static_cast<const T*>(b.in[0]), static_cast<V*>(b.out[0]), b.list,
+                           b.stab);
     }
     static void y_fwd(const PrunedBufs& b)
     {
@@ -108,10 +119,12 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
         hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((H + ZT - 1) / ZT, N, b.count), dim3(NTY),
                            0, b.stream, static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab);
     }
-    static void x_c2r(const PrunedBufs& b)
+    template <int ROWS = 16> static void x_c2r(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTX, MAP_EF, MT>), dim3((N + 15) / 16, N, b.count), dim3(NTX), 0,
-                           b.stream, static_cast<const V*>(b.in[4]), static_cast<T*>(b.out[4]), b.list, b.stab);
+        constexpr int NTR = threads_for(ROWS / 2, P, E);
+        hipLaunchKernelGGL((k_x_c2r<T, P, FAM, NTR, MAP_EF, MT, false, ROWS>), dim3((N + ROWS - 1) / ROWS, N, b.count),
+                           dim3(NTR), 0, b.stream, static_cast<const V*>(b.in[4]), static_cast<T*>(b.out[4]), b.list,
+                           b.stab);
     }
 
     // Box forms: P is the transformed axis's length; the grids cover the
@@ -171,6 +184,7 @@ template <typename T, int P, int MT> static hipError_t box_pass(int pass, const 
     const PrunedVariant& v = b.var;
     switch (pass) {
     case 0:
+        if (v.x_fam >> 1) return hipErrorInvalidValue;  // boxes: 16 rows per x tile
         if (v.x_fam == 1 && F1) L1::x_r2c_box(b);
         else L0::x_r2c_box(b);
         break;
@@ -190,6 +204,7 @@ template <typename T, int P, int MT> static hipError_t box_pass(int pass, const 
         else L0::y_inv_box(b);
         break;
     case 4:
+        if (v.xc_fam >> 1) return hipErrorInvalidValue;
         if (v.xc_fam == 1 && F1) L1::x_c2r_box(b);
         else L0::x_c2r_box(b);
         break;
@@ -197,6 +212,39 @@ template <typename T, int P, int MT> static hipError_t box_pass(int pass, const 
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// An x pass of a cube: variant = family (bit 0) + 2 x rows selector (0: 16
+// rows per workgroup, 1: 8, 2: 32).  False for a tile the LDS cannot hold.
+template <typename T, int P, int MT, int ROWS> static bool x_rows(bool inverse, bool fam1, const PrunedBufs& b)
+{
+    constexpr bool F1 = has_fam1<P>() && MT == 0;
+    using L0 = PassLaunch<T, P, 0, MT>;
+    using L1 = PassLaunch<T, P, F1 ? 1 : 0, MT>;
+    if (fam1 && F1) {
+        if constexpr (x_fits<T, P, F1 ? 1 : 0, ROWS, MT>()) {
+            if (inverse) L1::template x_c2r<ROWS>(b);
+            else L1::template x_r2c<ROWS>(b);
+            return true;
+        }
+        return false;
+    }
+    if constexpr (x_fits<T, P, 0, ROWS, MT>()) {
+        if (inverse) L0::template x_c2r<ROWS>(b);
+        else L0::template x_r2c<ROWS>(b);
+        return true;
+    }
+    return false;
+}
+template <typename T, int P, int MT> static bool x_pass(bool inverse, int variant, const PrunedBufs& b)
+{
+    const bool fam1 = variant & 1;
+    switch (variant >> 1) {
+    case 0: return x_rows<T, P, MT, 16>(inverse, fam1, b);
+    case 1: return x_rows<T, P, MT, 8>(inverse, fam1, b);
+    case 2: return x_rows<T, P, MT, 32>(inverse, fam1, b);
+    default: return false;
+    }
 }
 
 // The fused z pass of a cube with B pencils per workgroup, in form zmode.
@@ -233,8 +281,7 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
     for (int pass = lo; pass < hi; ++pass) {
         switch (pass) {
         case 0:
-            if (v.x_fam == 1 && F1) L1::x_r2c(b);
-            else L0::x_r2c(b);
+            if (!x_pass<T, P, MT>(false, v.x_fam, b)) return hipErrorInvalidValue;
             break;
         case 1:  // variant bit 0: radix-32 family, bit 1: persistent
             if ((v.y_fam & 1) && F1) (v.y_fam & 2) ? L1::y_fwd_pf(b) : L1::y_fwd(b);
@@ -249,8 +296,7 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else (v.yi_fam & 2) ? L0::y_inv_pf(b) : L0::y_inv(b);
             break;
         case 4:
-            if (v.xc_fam == 1 && F1) L1::x_c2r(b);
-            else L0::x_c2r(b);
+            if (!x_pass<T, P, MT>(true, v.xc_fam, b)) return hipErrorInvalidValue;
             break;
         default:
             return hipErrorInvalidValue;

@@ -351,7 +351,8 @@ const char* prec_name(ps_precision p)
     return "?";
 }
 
-int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 4 : 2; }  // pass 6 (z tile): 2
+// pass 6 (z tile): 2 values; x passes: family bit + 2 x rows selector (16, 8, 32 rows)
+int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 4 : 6; }
 
 // Whether variant v of a pass runs the radix-32-based plan family.
 bool variant_needs_family1(int pass, int v) { return pass == 6 ? false : pass == 2 ? v == 2 : (v & 1) != 0; }
@@ -383,11 +384,37 @@ int* variant_slot(ps::PrunedVariant& v, int pass)
     }
 }
 
+// LDS row pitch of a length-P pencil (complex elements of eb bytes) whose
+// plan starts with radix r0: the device engine's pad_pitch.
+int lds_pitch(int P, int r0, int eb)
+{
+    const int G = r0 == 32 ? 32 : 16;
+    const int lp = P + P / G + 1;
+    return eb == 16 ? lp + (12 - lp % 8) % 8 : lp;
+}
+
+// Whether both x passes with `rows` rows per workgroup fit the 160 KB of LDS
+// (the launchers' x_fits).
+bool x_rows_fit(ps_plan p, int rows, bool fam1)
+{
+    const int P = axis_pad(p, 0), H = P / 2 + 1, eb = 2 * (int)p->real_bytes;
+    std::vector<int> fwd;
+    if (!ps::host_radices(P, fwd, fam1 ? 1 : 0) || fwd.empty()) return false;
+    const int lf = (rows / 2) * lds_pitch(P, fwd.front(), eb);
+    const int li = std::max((rows / 2) * lds_pitch(P, fwd.back(), eb), rows * (H + 1));  // inverse plan reversed
+    return std::max(lf, li) * eb <= 160 * 1024;
+}
+
 // Whether `variant` is a kernel variant of `pass` that this plan can run.
 bool variant_ok(ps_plan p, int pass, int variant)
 {
     if (variant < 0 || variant >= num_variants(pass)) return false;
     if (variant_needs_family1(pass, variant) && !family1_available(p, pass)) return false;
+    if (pass == 0 || pass == 4) {
+        static const int ROWS[3] = {16, 8, 32};
+        if ((variant >> 1) != 0 && p->box) return false;  // boxes: 16 rows per x tile
+        if (!x_rows_fit(p, ROWS[variant >> 1], (variant & 1) && family1_available(p, pass))) return false;
+    }
     // boxes run the one-tile-per-workgroup kernels only
     if (p->box && (pass == 1 || pass == 3) && (variant & 2)) return false;
     if (p->box && pass == 2 && variant >= 3) return false;
@@ -395,8 +422,10 @@ bool variant_ok(ps_plan p, int pass, int variant)
 }
 
 // Default z pass per padded length: the fastest form (variant 0..4) and
-// tile width (0: full, 1: half) measured on MI355X for FP64, FP32 and
-// FP32-split.  P = 64, 96, 128, 192, 256 (the lengths of batches of uneven
+// tile width (0: full, 1: half), and for P > 256 the x passes' variants
+// (family and rows per workgroup; 8 rows won for most FP64 lengths and for
+// the inverse x pass of most FP32 lengths), measured on MI355X for FP64,
+// FP32 and FP32-split.  P = 64, 96, 128, 192, 256 (the lengths of batches of uneven
 // small solves): the wave-owned form on the full tile, the fastest for the
 // 96-solve batch as a whole (groups run side by side on forked streams,
 // where persistent forms, which fill the device, and the half tile measured
@@ -406,48 +435,46 @@ bool variant_ok(ps_plan p, int pass, int variant)
 struct ZDefault {
     int P;
     signed char zmode[3], ztile[3];  // [FP64, FP32, FP32-split]
+    signed char x[3], xc[3];         // x_r2c and x_c2r variants; -1: the family rule
 };
 const ZDefault Z_DEFAULTS[] = {
-    {  16, {1, 3, 1}, {0, 1, 0}},
-    {  32, {1, 1, 1}, {0, 0, 0}},
-    {  48, {1, 1, 0}, {0, 0, 1}},
-    {  64, {1, 1, 1}, {0, 0, 0}},
-    {  80, {1, 1, 0}, {0, 0, 1}},
-    {  96, {1, 1, 1}, {0, 0, 0}},
-    { 128, {1, 1, 1}, {0, 0, 0}},
-    { 144, {1, 1, 1}, {1, 0, 0}},
-    { 160, {1, 0, 0}, {0, 1, 0}},
-    { 192, {1, 1, 1}, {0, 0, 0}},
-    { 240, {1, 1, 4}, {1, 1, 1}},
-    { 256, {1, 1, 1}, {0, 0, 0}},
-    { 288, {0, 0, 1}, {0, 1, 1}},
-    { 320, {0, 0, 0}, {0, 1, 1}},
-    { 384, {0, 0, 0}, {0, 1, 1}},
-    { 400, {4, 4, 1}, {0, 1, 0}},
-    { 432, {1, 1, 1}, {0, 0, 0}},
-    { 480, {1, 1, 1}, {0, 0, 1}},
-    { 512, {4, 3, 4}, {0, 0, 1}},
-    { 576, {1, 1, 1}, {0, 0, 0}},
-    { 640, {1, 3, 1}, {1, 1, 1}},
-    { 720, {0, 1, 1}, {1, 0, 0}},
-    { 768, {0, 0, 1}, {1, 1, 1}},
-    { 800, {4, 1, 1}, {0, 0, 0}},
-    { 864, {1, 4, 1}, {0, 1, 0}},
-    { 960, {1, 1, 1}, {0, 0, 0}},
-    {1024, {2, 3, 1}, {1, 0, 1}},
+    {  16, {1, 3, 1}, {0, 1, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    {  32, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    {  48, {1, 1, 0}, {0, 0, 1}, {-1, -1, -1}, {-1, -1, -1}},
+    {  64, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    {  80, {1, 1, 0}, {0, 0, 1}, {-1, -1, -1}, {-1, -1, -1}},
+    {  96, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    { 128, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    { 144, {1, 1, 1}, {1, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    { 160, {1, 0, 0}, {0, 1, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    { 192, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    { 240, {1, 1, 4}, {1, 1, 1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 256, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
+    { 288, {0, 0, 1}, {0, 1, 1}, {2, 2, 4}, {-1, 2, 4}},
+    { 320, {0, 0, 0}, {0, 1, 1}, {2, 2, -1}, {-1, -1, -1}},
+    { 384, {0, 0, 0}, {0, 1, 1}, {-1, -1, -1}, {2, -1, -1}},
+    { 400, {4, 4, 1}, {0, 1, 0}, {2, 2, 2}, {2, 2, -1}},
+    { 432, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}},
+    { 480, {1, 1, 1}, {0, 0, 1}, {-1, -1, -1}, {2, 2, 2}},
+    { 512, {4, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}},
+    { 576, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}},
+    { 640, {1, 3, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}},
+    { 720, {0, 1, 1}, {1, 0, 0}, {2, -1, -1}, {2, 2, 2}},
+    { 768, {0, 0, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}},
+    { 800, {4, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}},
+    { 864, {1, 4, 1}, {0, 1, 0}, {2, -1, -1}, {2, 2, 2}},
+    { 960, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}},
+    {1024, {2, 3, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, -1}},
 };
 
-bool z_default(int P, ps_precision prec, int& zmode, int& ztile)
+// The measured defaults of length P, and the precision's column in them.
+const ZDefault* measured_default(int P, ps_precision prec, int& k)
 {
-    const int k = prec == PS_F64 ? 0 : prec == PS_F32 ? 1 : prec == PS_F32_SPLIT ? 2 : -1;
-    if (k < 0) return false;
+    k = prec == PS_F64 ? 0 : prec == PS_F32 ? 1 : prec == PS_F32_SPLIT ? 2 : -1;
+    if (k < 0) return nullptr;
     for (const ZDefault& d : Z_DEFAULTS)
-        if (d.P == P) {
-            zmode = d.zmode[k];
-            ztile = d.ztile[k];
-            return true;
-        }
-    return false;
+        if (d.P == P) return &d;
+    return nullptr;
 }
 
 // Tuning cache: one line per (P, precision): "P prec x y z yi xc zt" (zt,
@@ -625,13 +652,18 @@ ps_status create_plan(ps_plan* out, int nx, int ny, int nz, double dx, double dy
         p->var.zmode = 1;
     }
     // the z pass's form and tile width per length, as measured (boxes take
-    // the one-tile-per-workgroup forms only)
+    // the one-tile-per-workgroup forms only), and the x passes' rows per
+    // workgroup where the table has them (cubes)
     if (!is_plain(prec)) {
-        int zm = 0, zt = 0;
-        if (z_default(Pz, prec, zm, zt) && (!box || zm <= 2)) {
-            p->var.zmode = zm;
-            p->var.ztile = zt;
+        int k = 0;
+        const ZDefault* d = measured_default(Pz, prec, k);
+        if (d && (!box || d->zmode[k] <= 2)) {
+            p->var.zmode = d->zmode[k];
+            p->var.ztile = d->ztile[k];
         }
+        d = box ? nullptr : measured_default(p->P, prec, k);
+        if (d && d->x[k] >= 0 && variant_ok(p, 0, d->x[k])) p->var.x_fam = d->x[k];
+        if (d && d->xc[k] >= 0 && variant_ok(p, 4, d->xc[k])) p->var.xc_fam = d->xc[k];
     }
     if (tune_cache && !is_plain(prec) && !box) read_tuning(tune_cache, p);
     const size_t Ny = ny, Nz = nz, Hx = nx + 1, Hy = ny + 1, Hz = nz + 1;
@@ -950,7 +982,9 @@ ps_status ps_plan_set_variant(ps_plan p, int pass, int variant)
     if (variant_needs_family1(pass, variant) && !family1_available(p, pass))
         return fail(PS_ERR_UNSUPPORTED, "this plan has no radix-32 plan family");
     if (!variant_ok(p, pass, variant))
-        return fail(PS_ERR_UNSUPPORTED, "boxes run the one-tile-per-workgroup kernels (no persistent variants)");
+        return fail(PS_ERR_UNSUPPORTED, (pass == 0 || pass == 4)
+                                            ? "this x tile does not fit the LDS, or boxes (16 rows per x tile only)"
+                                            : "boxes run the one-tile-per-workgroup kernels (no persistent variants)");
     *variant_slot(p->var, pass) = variant;
     return PS_OK;
 }

@@ -326,7 +326,7 @@ def test_variants_agree_n256(prec):
         S.ps_plan_set_variant(s.plan, k, 0)
     base = s(rho).double().cpu().numpy()
     tol = 1e-13 if prec == "f64" else 5e-7
-    for k, nv in zip(range(5), (2, 4, 5, 4, 2)):
+    for k, nv in zip(range(5), (6, 4, 5, 4, 6)):
         for v in range(1, nv):
             S.ps_plan_set_variant(s.plan, k, v)
             got = s(rho).double().cpu().numpy()
@@ -359,6 +359,22 @@ def test_zmodes_match_oracle(prec, n, zmode, ztile):
     ref = oracle.fft_conv(r.double().cpu().numpy(), 1.0 / n)
     l2, _ = _report(f"zmode {zmode} ztile {ztile} n={n} {prec}", got, ref)
     assert l2 <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
+@pytest.mark.parametrize("n", [24, 40, 120, 200])
+def test_x_rows_match_oracle(prec, n):
+    # 8, 16 and 32 rows per x-pass workgroup (ragged last y tiles at these n)
+    rho = inputs.make_density(n, 5, 700 + n, sigma=(0.03, 0.1), noise=1e-3)
+    s = S.Solver(n, 1.0 / n, prec)
+    r = torch.from_numpy(rho).to("cuda", _dtype(prec))
+    ref = oracle.fft_conv(r.double().cpu().numpy(), 1.0 / n)
+    for v in (0, 2, 4):
+        S.ps_plan_set_variant(s.plan, 0, v)
+        S.ps_plan_set_variant(s.plan, 4, v)
+        got = s(r).double().cpu().numpy()
+        l2, _ = _report(f"x rows variant {v} n={n} {prec}", got, ref)
+        assert l2 <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
