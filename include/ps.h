@@ -211,7 +211,9 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = radix-32-
  * based plan (n = 256 and 512 only); passes 1 and 3 (the y passes) also
  * take 2 and 3, the same plans run by persistent workgroups that load the
- * next tile while transforming the current one; passes 0 and 4 (the x
+ * next tile while transforming the current one, and 4 and 5, the plans of 0
+ * and 1 with half as many pencils per workgroup (8 in float, 4 in double:
+ * 64-byte output rows, half the LDS); passes 0 and 4 (the x
  * passes) also take 2 and 3 (8 rows of a z-plane per workgroup instead of
  * 16) and 4 and 5 (32 rows, where the LDS holds them; PS_ERR_UNSUPPORTED
  * otherwise), the family again in the low bit.  Pass 2 (the fused z pass): 0 =

@@ -73,9 +73,11 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
                            dim3(NTR), 0, b.stream, static_cast<const T*>(b.in[0]), static_cast<V*>(b.out[0]), b.list,
                            b.stab);
     }
-    static void y_fwd(const PrunedBufs& b)
+    // y passes: Z pencils per workgroup (the full tile ZT or half of it)
+    template <int Z = ZT> static void y_fwd(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((N + ZT - 1) / ZT, H, b.count), dim3(NTY),
+        constexpr int NTZY = threads_for(Z, P, E);
+        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, Z, NTZY, MAP_EF, MT>), dim3((N + Z - 1) / Z, H, b.count), dim3(NTZY),
                            0, b.stream, static_cast<const V*>(b.in[1]), static_cast<V*>(b.out[1]), b.list, b.stab);
     }
     // z pass: B pencils per workgroup (the full tile ZB or half of it)
@@ -114,9 +116,10 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
                            0, b.stream, static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab,
                            b.count);
     }
-    static void y_inv(const PrunedBufs& b)
+    template <int Z = ZT> static void y_inv(const PrunedBufs& b)
     {
-        hipLaunchKernelGGL((k_y_inv<T, P, FAM, ZT, NTY, MAP_EF, MT>), dim3((H + ZT - 1) / ZT, N, b.count), dim3(NTY),
+        constexpr int NTZY = threads_for(Z, P, E);
+        hipLaunchKernelGGL((k_y_inv<T, P, FAM, Z, NTZY, MAP_EF, MT>), dim3((H + Z - 1) / Z, N, b.count), dim3(NTZY),
                            0, b.stream, static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab);
     }
     template <int ROWS = 16> static void x_c2r(const PrunedBufs& b)
@@ -189,7 +192,7 @@ template <typename T, int P, int MT> static hipError_t box_pass(int pass, const 
         else L0::x_r2c_box(b);
         break;
     case 1:
-        if (v.y_fam & 2) return hipErrorInvalidValue;
+        if (v.y_fam & 6) return hipErrorInvalidValue;  // boxes: one tile per workgroup, full tile
         if ((v.y_fam & 1) && F1) L1::y_fwd_box(b);
         else L0::y_fwd_box(b);
         break;
@@ -199,7 +202,7 @@ template <typename T, int P, int MT> static hipError_t box_pass(int pass, const 
         else box_z<T, P, MT, PrunedShape<T>::ZB>(v.zmode, b);
         break;
     case 3:
-        if (v.yi_fam & 2) return hipErrorInvalidValue;
+        if (v.yi_fam & 6) return hipErrorInvalidValue;
         if ((v.yi_fam & 1) && F1) L1::y_inv_box(b);
         else L0::y_inv_box(b);
         break;
@@ -284,7 +287,11 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             if (!x_pass<T, P, MT>(false, v.x_fam, b)) return hipErrorInvalidValue;
             break;
         case 1:  // variant bit 0: radix-32 family, bit 1: persistent
-            if ((v.y_fam & 1) && F1) (v.y_fam & 2) ? L1::y_fwd_pf(b) : L1::y_fwd(b);
+            // variant bit 0: radix-32 family, bit 1: persistent, 4 and 5: half tile
+            if (v.y_fam >= 4) {
+                if ((v.y_fam & 1) && F1) L1::template y_fwd<PrunedShape<T>::ZT / 2>(b);
+                else L0::template y_fwd<PrunedShape<T>::ZT / 2>(b);
+            } else if ((v.y_fam & 1) && F1) (v.y_fam & 2) ? L1::y_fwd_pf(b) : L1::y_fwd(b);
             else (v.y_fam & 2) ? L0::y_fwd_pf(b) : L0::y_fwd(b);
             break;
         case 2:
@@ -292,7 +299,10 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else cube_z<T, P, MT, PrunedShape<T>::ZB>(v.zmode, b);
             break;
         case 3:
-            if ((v.yi_fam & 1) && F1) (v.yi_fam & 2) ? L1::y_inv_pf(b) : L1::y_inv(b);
+            if (v.yi_fam >= 4) {
+                if ((v.yi_fam & 1) && F1) L1::template y_inv<PrunedShape<T>::ZT / 2>(b);
+                else L0::template y_inv<PrunedShape<T>::ZT / 2>(b);
+            } else if ((v.yi_fam & 1) && F1) (v.yi_fam & 2) ? L1::y_inv_pf(b) : L1::y_inv(b);
             else (v.yi_fam & 2) ? L0::y_inv_pf(b) : L0::y_inv(b);
             break;
         case 4:
@@ -309,12 +319,18 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
 
 // Passes [lo, hi): a cube's run on its one length; a box's each on the
 // length of the axis it transforms (x: passes 0 and 4, y: 1 and 3, z: 2).
-template <typename T, int MT> static hipError_t pruned_dispatch(int lo, int hi, const PrunedBufs& b)
+// Only the lengths of one half (is_short_p(P) == SHORT) are instantiated
+// here, so that each arithmetic compiles as two units in parallel; the
+// other half returns hipErrorInvalidValue (pruned_run in ps_internal.hpp
+// routes every pass to its half).
+template <typename T, int MT, bool SHORT> static hipError_t pruned_dispatch(int lo, int hi, const PrunedBufs& b)
 {
     if (!b.box) {
         switch (b.px) {
-#define PS_CASE(PP) \
-    case PP: return pruned_passes<T, PP, MT>(lo, hi, b);
+#define PS_CASE(PP)                                                           \
+    case PP:                                                                  \
+        if constexpr (is_short_p(PP) == SHORT) return pruned_passes<T, PP, MT>(lo, hi, b); \
+        else return hipErrorInvalidValue;
             PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
         default: return hipErrorInvalidValue;
@@ -324,8 +340,10 @@ template <typename T, int MT> static hipError_t pruned_dispatch(int lo, int hi, 
         const int P = pass == 2 ? b.pz : (pass == 1 || pass == 3) ? b.py : b.px;
         hipError_t e = hipErrorInvalidValue;
         switch (P) {
-#define PS_CASE(PP) \
-    case PP: e = box_pass<T, PP, MT>(pass, b); break;
+#define PS_CASE(PP)                                                           \
+    case PP:                                                                  \
+        if constexpr (is_short_p(PP) == SHORT) e = box_pass<T, PP, MT>(pass, b); \
+        break;
             PS_FOR_EACH_P(PS_CASE)
 #undef PS_CASE
         default: break;

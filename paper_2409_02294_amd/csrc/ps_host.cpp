@@ -351,8 +351,9 @@ const char* prec_name(ps_precision p)
     return "?";
 }
 
-// pass 6 (z tile): 2 values; x passes: family bit + 2 x rows selector (16, 8, 32 rows)
-int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 4 : 6; }
+// pass 6 (z tile): 2 values; x passes: family bit + 2 x rows selector (16, 8, 32 rows);
+// y passes: family bit + 2 x persistent bit, or 4 + family bit (half tile)
+int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : 6; }
 
 // Whether variant v of a pass runs the radix-32-based plan family.
 bool variant_needs_family1(int pass, int v) { return pass == 6 ? false : pass == 2 ? v == 2 : (v & 1) != 0; }
@@ -416,7 +417,7 @@ bool variant_ok(ps_plan p, int pass, int variant)
         if (!x_rows_fit(p, ROWS[variant >> 1], (variant & 1) && family1_available(p, pass))) return false;
     }
     // boxes run the one-tile-per-workgroup kernels only
-    if (p->box && (pass == 1 || pass == 3) && (variant & 2)) return false;
+    if (p->box && (pass == 1 || pass == 3) && (variant & 6)) return false;
     if (p->box && pass == 2 && variant >= 3) return false;
     return true;
 }
@@ -424,8 +425,9 @@ bool variant_ok(ps_plan p, int pass, int variant)
 // Default z pass per padded length: the fastest form (variant 0..4) and
 // tile width (0: full, 1: half), and for P > 256 the x passes' variants
 // (family and rows per workgroup; 8 rows won for most FP64 lengths and for
-// the inverse x pass of most FP32 lengths), measured on MI355X for FP64,
-// FP32 and FP32-split.  P = 64, 96, 128, 192, 256 (the lengths of batches of uneven
+// the inverse x pass of most FP32 lengths) and the y passes' (family,
+// persistent form or half tile), measured on MI355X for FP64, FP32 and
+// FP32-split.  P = 64, 96, 128, 192, 256 (the lengths of batches of uneven
 // small solves): the wave-owned form on the full tile, the fastest for the
 // 96-solve batch as a whole (groups run side by side on forked streams,
 // where persistent forms, which fill the device, and the half tile measured
@@ -436,35 +438,36 @@ struct ZDefault {
     int P;
     signed char zmode[3], ztile[3];  // [FP64, FP32, FP32-split]
     signed char x[3], xc[3];         // x_r2c and x_c2r variants; -1: the family rule
+    signed char y[3], yi[3];         // forward and inverse y-pass variants; -1: the family rule
 };
 const ZDefault Z_DEFAULTS[] = {
-    {  16, {1, 3, 1}, {0, 1, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    {  32, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    {  48, {1, 1, 0}, {0, 0, 1}, {-1, -1, -1}, {-1, -1, -1}},
-    {  64, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    {  80, {1, 1, 0}, {0, 0, 1}, {-1, -1, -1}, {-1, -1, -1}},
-    {  96, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    { 128, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    { 144, {1, 1, 1}, {1, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    { 160, {1, 0, 0}, {0, 1, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    { 192, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    { 240, {1, 1, 4}, {1, 1, 1}, {-1, -1, -1}, {-1, -1, -1}},
-    { 256, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}},
-    { 288, {0, 0, 1}, {0, 1, 1}, {2, 2, 4}, {-1, 2, 4}},
-    { 320, {0, 0, 0}, {0, 1, 1}, {2, 2, -1}, {-1, -1, -1}},
-    { 384, {0, 0, 0}, {0, 1, 1}, {-1, -1, -1}, {2, -1, -1}},
-    { 400, {4, 4, 1}, {0, 1, 0}, {2, 2, 2}, {2, 2, -1}},
-    { 432, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}},
-    { 480, {1, 1, 1}, {0, 0, 1}, {-1, -1, -1}, {2, 2, 2}},
-    { 512, {4, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}},
-    { 576, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}},
-    { 640, {1, 3, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}},
-    { 720, {0, 1, 1}, {1, 0, 0}, {2, -1, -1}, {2, 2, 2}},
-    { 768, {0, 0, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}},
-    { 800, {4, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}},
-    { 864, {1, 4, 1}, {0, 1, 0}, {2, -1, -1}, {2, 2, 2}},
-    { 960, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}},
-    {1024, {2, 3, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, -1}},
+    {  16, {1, 3, 1}, {0, 1, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    {  32, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    {  48, {1, 1, 0}, {0, 0, 1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    {  64, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    {  80, {1, 1, 0}, {0, 0, 1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    {  96, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 128, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 144, {1, 1, 1}, {1, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 160, {1, 0, 0}, {0, 1, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 192, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 240, {1, 1, 4}, {1, 1, 1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 256, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 288, {0, 0, 1}, {0, 1, 1}, {2, 2, 4}, {-1, 2, 4}, {-1, -1, -1}, {-1, -1, -1}},
+    { 320, {0, 0, 0}, {0, 1, 1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 384, {0, 0, 0}, {0, 1, 1}, {-1, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 400, {4, 4, 1}, {0, 1, 0}, {2, 2, 2}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 432, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 480, {1, 1, 1}, {0, 0, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, -1, -1}, {-1, -1, -1}},
+    { 512, {4, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
+    { 576, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}, {2, 4, 4}, {4, 4, -1}},
+    { 640, {1, 3, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, -1, 2}, {4, -1, 4}},
+    { 720, {0, 1, 1}, {1, 0, 0}, {2, -1, -1}, {2, 2, 2}, {-1, 4, 4}, {4, 4, 4}},
+    { 768, {0, 0, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, -1, -1}, {-1, -1, 4}},
+    { 800, {4, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {4, 4, 4}},
+    { 864, {1, 4, 1}, {0, 1, 0}, {2, -1, -1}, {2, 2, 2}, {2, 4, -1}, {-1, -1, 4}},
+    { 960, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, 4, 4}},
+    {1024, {2, 3, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, 4}},
 };
 
 // The measured defaults of length P, and the precision's column in them.
@@ -664,6 +667,8 @@ ps_status create_plan(ps_plan* out, int nx, int ny, int nz, double dx, double dy
         d = box ? nullptr : measured_default(p->P, prec, k);
         if (d && d->x[k] >= 0 && variant_ok(p, 0, d->x[k])) p->var.x_fam = d->x[k];
         if (d && d->xc[k] >= 0 && variant_ok(p, 4, d->xc[k])) p->var.xc_fam = d->xc[k];
+        if (d && d->y[k] >= 0 && variant_ok(p, 1, d->y[k])) p->var.y_fam = d->y[k];
+        if (d && d->yi[k] >= 0 && variant_ok(p, 3, d->yi[k])) p->var.yi_fam = d->yi[k];
     }
     if (tune_cache && !is_plain(prec) && !box) read_tuning(tune_cache, p);
     const size_t Ny = ny, Nz = nz, Hx = nx + 1, Hy = ny + 1, Hz = nz + 1;

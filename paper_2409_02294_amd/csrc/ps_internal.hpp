@@ -54,10 +54,44 @@ struct PrunedBufs {
 // Runs passes [lo, hi) of the pruned pipeline (0 x_r2c, 1 y_fwd, 2 z_conv,
 // 3 y_inv, 4 x_c2r), each on its axis's padded length.  Returns
 // hipErrorInvalidValue for an unsupported length or a variant boxes lack.
-hipError_t pruned_run_f32(int lo, int hi, const PrunedBufs& b);
-hipError_t pruned_run_f64(int lo, int hi, const PrunedBufs& b);
-hipError_t pruned_run_split6(int lo, int hi, const PrunedBufs& b);
-hipError_t pruned_run_split3(int lo, int hi, const PrunedBufs& b);
+// Each arithmetic is compiled as two units, one per half of the lengths
+// (is_short_p); pruned_run sends every pass to the half of its length.
+constexpr bool is_short_p(int P) { return P <= 480; }
+using PrunedRunFn = hipError_t (*)(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_f32_short(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_f32_long(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_f64_short(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_f64_long(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split6_short(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split6_long(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split3_short(int lo, int hi, const PrunedBufs& b);
+hipError_t pruned_run_split3_long(int lo, int hi, const PrunedBufs& b);
+inline hipError_t pruned_run(PrunedRunFn fshort, PrunedRunFn flong, int lo, int hi, const PrunedBufs& b)
+{
+    if (!b.box) return (is_short_p(b.px) ? fshort : flong)(lo, hi, b);
+    for (int pass = lo; pass < hi; ++pass) {
+        const int P = pass == 2 ? b.pz : (pass == 1 || pass == 3) ? b.py : b.px;
+        const hipError_t e = (is_short_p(P) ? fshort : flong)(pass, pass + 1, b);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+inline hipError_t pruned_run_f32(int lo, int hi, const PrunedBufs& b)
+{
+    return pruned_run(pruned_run_f32_short, pruned_run_f32_long, lo, hi, b);
+}
+inline hipError_t pruned_run_f64(int lo, int hi, const PrunedBufs& b)
+{
+    return pruned_run(pruned_run_f64_short, pruned_run_f64_long, lo, hi, b);
+}
+inline hipError_t pruned_run_split6(int lo, int hi, const PrunedBufs& b)
+{
+    return pruned_run(pruned_run_split6_short, pruned_run_split6_long, lo, hi, b);
+}
+inline hipError_t pruned_run_split3(int lo, int hi, const PrunedBufs& b)
+{
+    return pruned_run(pruned_run_split3_short, pruned_run_split3_long, lo, hi, b);
+}
 
 // Transformed-kernel build (double precision throughout), on a box of
 // nx x ny x nz cells (a cube when all three are equal).

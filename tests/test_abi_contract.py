@@ -161,6 +161,11 @@ def test_variant_selection_contract():
         assert lib.ps_plan_set_variant(p, 0, 2) == S.PS_OK and lib.ps_plan_set_variant(p, 4, 4) == S.PS_OK
         assert lib.ps_plan_set_variant(p, 0, 3) == S.PS_ERR_UNSUPPORTED  # 8 rows, radix-32 family: none at P = 64
         assert lib.ps_plan_set_variant(p, 0, 6) == S.PS_ERR_INVALID
+        # y passes: half tile (4: radix-16 family, 5: radix-32 family)
+        assert lib.ps_plan_set_variant(p, 1, 4) == S.PS_OK and lib.ps_plan_set_variant(p, 3, 4) == S.PS_OK
+        assert lib.ps_plan_set_variant(p, 1, 5) == S.PS_ERR_UNSUPPORTED
+        assert lib.ps_plan_set_variant(p, 3, 6) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(q, 3, 5) == S.PS_OK
         assert lib.ps_plan_set_variant(q, 4, 5) == S.PS_OK               # 32 rows, radix-32 family, FP64 P = 512
         r = S.ps_plan_create(512, 1.0 / 512, S.PS_F64)
         try:
@@ -248,8 +253,8 @@ def test_tuning_cache_is_read(tmp_path):
         S.ps_plan_destroy(p)
     # measured defaults: variants and z tile
     for n, prec, want, zt in [(512, S.PS_F32, [0, 1, 3, 3, 2], 0), (512, S.PS_F64, [2, 1, 2, 2, 2], 1),
-                              (256, S.PS_F64, [2, 1, 4, 0, 2], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 0, 2], 1),
-                              (128, S.PS_F32, [0, 0, 1, 0, 0], 0), (512, S.PS_F32_SPLIT, [0, 0, 1, 0, 0], 1),
+                              (256, S.PS_F64, [2, 1, 4, 0, 2], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 4, 2], 1),
+                              (128, S.PS_F32, [0, 0, 1, 0, 0], 0), (512, S.PS_F32_SPLIT, [0, 0, 1, 4, 0], 1),
                               (384, S.PS_F32, [0, 0, 0, 0, 2], 1), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
         try:
@@ -264,7 +269,7 @@ def test_split_plan_contract():
     try:
         info = S.ps_plan_query(p)
         assert info["split_terms"] == 6
-        assert info["variant"] == [0, 0, 4, 0, 0] and info["z_tile"] == 1
+        assert info["variant"] == [0, 0, 4, 4, 0] and info["z_tile"] == 1
         lib = S.load()
         assert lib.ps_plan_set_variant(p, 5, 4) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # keeps the radix-16 family
@@ -346,6 +351,7 @@ def test_box_plan_contract():
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED   # P = 48 along z: no radix-32 family
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # P = 80 along x: no radix-32 family
         assert lib.ps_plan_set_variant(p, 0, 2) == S.PS_ERR_UNSUPPORTED   # boxes: 16 rows per x tile
+        assert lib.ps_plan_set_variant(p, 1, 4) == S.PS_ERR_UNSUPPORTED   # boxes: full y tile
         assert lib.ps_plan_set_variant(p, 4, 4) == S.PS_ERR_UNSUPPORTED
         assert lib.ps_plan_set_variant(p, 3, 1) == S.PS_OK
         assert lib.ps_solve(p, 0x100000, 0x10000000, None) == S.PS_ERR_NOT_READY
