@@ -209,7 +209,8 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
 
 /* Choose the kernel variant of one pass of a pruned plan (host only, no HIP
  * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = radix-32-
- * based plan (n = 256 and 512 only); passes 1 and 3 (the y passes) also
+ * based plan (two stages; n = 256, 320, 384, 480 and 512 only); passes 1 and
+ * 3 (the y passes) also
  * take 2 and 3, the same plans run by persistent workgroups that load the
  * next tile while transforming the current one, and 4 and 5, the plans of 0
  * and 1 with half as many pencils per workgroup (8 in float, 4 in double:
@@ -218,8 +219,8 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * 16) and 4 and 5 (32 rows, where the LDS holds them; PS_ERR_UNSUPPORTED
  * otherwise), the family again in the low bit.  Pass 2 (the fused z pass): 0 =
  * workgroup-synchronised pencils, 1 = wavefront-owned pencils, 2 =
- * wavefront-owned pencils on the radix-32-based plan (n = 256, 512; else
- * as 1), 3 = persistent workgroups that load the next tile while
+ * wavefront-owned pencils on the radix-32-based plan (n = 256, 320, 384,
+ * 480, 512; else as 1), 3 = persistent workgroups that load the next tile while
  * transforming the current one (radix-32-based plan where it exists, else
  * radix-16-based), 4 = persistent on the radix-16-based plan with fewer
  * pencils per wavefront.  Boxes (ps_plan_create_box with unequal lengths)

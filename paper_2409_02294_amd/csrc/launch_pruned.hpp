@@ -35,7 +35,7 @@ template <typename T, int P, int FAM, int EL, int MT, int B = PrunedShape<T>::ZB
 // Whether the x passes with ROWS rows per workgroup fit the LDS.
 template <typename T, int P, int FAM, int ROWS, int MT> constexpr bool x_fits()
 {
-    constexpr int NTR = threads_for(ROWS / 2, P, FAM == 1 ? 32 : 16);
+    constexpr int NTR = threads_for(ROWS / 2, P, FAM == 1 ? fam1_elems<P>() : 16);
     return TileXR2C<T, P, FAM, NTR, MAP_EF, MT, false, ROWS>::LDS * (int)sizeof(cx<T>) <= 160 * 1024 &&
            TileXC2R<T, P, FAM, NTR, MAP_EF, MT, false, ROWS>::LDS * (int)sizeof(cx<T>) <= 160 * 1024;
 }
@@ -60,8 +60,8 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
     // z pass of split plans also takes 32 (its matrix-core DFT-16 operands
     // and accumulators need the register budget of half as many threads:
     // at 16 the compiler spilled and the pass moved 1.4x its bytes)
-    static constexpr int E = FAM == 1 ? 32 : 16;
-    static constexpr int EZ = (FAM == 1 || MT > 0) ? 32 : 16;
+    static constexpr int E = FAM == 1 ? fam1_elems<P>() : 16;
+    static constexpr int EZ = FAM == 1 ? fam1_elems<P>() : MT > 0 ? 32 : 16;
     static constexpr int NTX = threads_for(8, P, E);
     static constexpr int NTY = threads_for(ZT, P, E);
 
@@ -256,7 +256,6 @@ template <typename T, int P, int MT, int B> static void cube_z(int zmode, const 
     using L0 = PassLaunch<T, P, 0, MT>;
     constexpr bool F1 = has_fam1<P>() && MT == 0;
     using L1 = PassLaunch<T, P, F1 ? 1 : 0, MT>;
-    // (a persistent form that does not fit in LDS runs as the wave-owned pass)
     if constexpr (PlanFor<P, F1 ? 1 : 0>::Fwd::S > 1 && z_pf_fits<T, P, F1 ? 1 : 0, 32, MT, B>()) {
         if (zmode == 3) {  // persistent: radix-32 family where it exists
             L1::template z_conv_pf<32, B>(b);
@@ -269,7 +268,8 @@ template <typename T, int P, int MT, int B> static void cube_z(int zmode, const 
             return;
         }
     }
-    if (zmode >= 2 && F1) L1::template z_conv<true, B>(b);
+    // (a persistent form that does not fit runs as the wave-owned pass of its own family)
+    if ((zmode == 2 || zmode == 3) && F1) L1::template z_conv<true, B>(b);
     else if (zmode >= 1) L0::template z_conv<true, B>(b);
     else L0::template z_conv<false, B>(b);
 }

@@ -282,6 +282,8 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
     else if constexpr (R == 12) dft_pfa<DIR, 4, 3>(v);
     else if constexpr (R == 15) dft_pfa<DIR, 3, 5>(v);
     else if constexpr (R == 20) dft_pfa<DIR, 4, 5>(v);
+    else if constexpr (R == 24) dft_pfa<DIR, 8, 3>(v);
+    else if constexpr (R == 30) dft_pfa<DIR, 2, 15>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
     else if constexpr (R == 32) dft32<DIR>(v);

@@ -461,12 +461,12 @@ const ZDefault Z_DEFAULTS[] = {
     { 480, {1, 1, 1}, {0, 0, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, -1, -1}, {-1, -1, -1}},
     { 512, {4, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
     { 576, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}, {2, 4, 4}, {4, 4, -1}},
-    { 640, {1, 3, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, -1, 2}, {4, -1, 4}},
+    { 640, {1, 2, 1}, {1, 1, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
     { 720, {0, 1, 1}, {1, 0, 0}, {2, -1, -1}, {2, 2, 2}, {-1, 4, 4}, {4, 4, 4}},
-    { 768, {0, 0, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, -1, -1}, {-1, -1, 4}},
+    { 768, {0, 2, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 1, -1}, {-1, -1, 4}},
     { 800, {4, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {4, 4, 4}},
     { 864, {1, 4, 1}, {0, 1, 0}, {2, -1, -1}, {2, 2, 2}, {2, 4, -1}, {-1, -1, 4}},
-    { 960, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, 4, 4}},
+    { 960, {2, 2, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {-1, 4, 4}},
     {1024, {2, 3, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, 4}},
 };
 
@@ -644,9 +644,9 @@ ps_status create_plan(ps_plan* out, int nx, int ny, int nz, double dx, double dy
         p->var.zmode = 1;
         p->var.mterms = 6;
     } else if (box) {
-        p->var.y_fam = ps::has_family1(Py) ? 1 : 0;
-        p->var.zmode = ps::has_family1(Pz) && !(prec == PS_F64 && Pz >= 1024) ? 2 : 1;
-    } else if (ps::has_family1(p->P)) {
+        p->var.y_fam = (Py == 512 || Py == 1024) ? 1 : 0;
+        p->var.zmode = (Pz == 512 || Pz == 1024) && !(prec == PS_F64 && Pz >= 1024) ? 2 : 1;
+    } else if (p->P == 512 || p->P == 1024) {
         p->var.y_fam = 1;
         p->var.zmode = prec == PS_F64 ? (p->P >= 1024 ? 1 : 2) : 3;
         if (p->P >= 1024) p->var.yi_fam = prec == PS_F64 ? 2 : 3;  // persistent inverse y pass

@@ -255,7 +255,7 @@ def test_tuning_cache_is_read(tmp_path):
     for n, prec, want, zt in [(512, S.PS_F32, [0, 1, 3, 3, 2], 0), (512, S.PS_F64, [2, 1, 2, 2, 2], 1),
                               (256, S.PS_F64, [2, 1, 4, 0, 2], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 4, 2], 1),
                               (128, S.PS_F32, [0, 0, 1, 0, 0], 0), (512, S.PS_F32_SPLIT, [0, 0, 1, 4, 0], 1),
-                              (384, S.PS_F32, [0, 0, 0, 0, 2], 1), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
+                              (384, S.PS_F32, [0, 1, 2, 0, 2], 1), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
         try:
             info = S.ps_plan_query(p)

@@ -361,6 +361,39 @@ def test_zmodes_match_oracle(prec, n, zmode, ztile):
     assert l2 <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [320, 384, 480])
+def test_two_stage_radix32_family(prec, n):
+    # P = 640, 768, 960 as radix 32 by a prime-factor radix (20, 24, 30):
+    # every variant on that family agrees with the radix-16-based plan to
+    # rounding, and the solve matches direct sums at sampled cells
+    rho_np = inputs.make_density(n, 12, 800 + n, sigma=(0.02, 0.06), noise=1e-3)
+    s = S.Solver(n, 1.0 / n, prec)
+    rho = torch.from_numpy(rho_np).to("cuda", _dtype(prec))
+    for k in range(5):
+        S.ps_plan_set_variant(s.plan, k, 0)
+    base = s(rho).double()
+    tol = 1e-13 if prec == "f64" else 5e-7
+    for k, vs in ((0, (1, 3)), (1, (1, 3, 5)), (2, (2, 3)), (3, (1, 3, 5)), (4, (1, 3))):
+        for v in vs:
+            try:
+                S.ps_plan_set_variant(s.plan, k, v)
+            except S.PSError:
+                continue  # a tile the LDS cannot hold
+            err = float((s(rho).double() - base).norm() / base.norm())
+            print(f"n={n} {prec} pass {k} variant {v}: relL2 vs radix-16 plan = {err:.2e}", flush=True)
+            assert err <= tol, (k, v, err)
+        S.ps_plan_set_variant(s.plan, k, 0)
+    for k, v in ((0, 1), (1, 1), (2, 2), (3, 1), (4, 1)):
+        S.ps_plan_set_variant(s.plan, k, v)
+    got = s(rho).double().cpu().numpy()
+    rho64 = rho.double().cpu().numpy()
+    cells = _sample_cells(n, 6, 5)
+    ref = oracle.direct_sum_cells(rho64, cells, 1.0 / n)
+    err = np.abs(got[cells[:, 0], cells[:, 1], cells[:, 2]] - ref).max() / np.abs(ref).max()
+    assert err <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 @pytest.mark.parametrize("n", [24, 40, 120, 200])
 def test_x_rows_match_oracle(prec, n):
@@ -401,17 +434,22 @@ def test_z_tile_widths_agree(prec, n):
 
 
 def test_persistent_z_fallback_where_lds_is_short():
-    # FP64 at P = 960: the persistent z pass does not fit in LDS, so variants
-    # 3 and 4 run the wave-owned pass (the same kernel as variant 1)
+    # FP64 at P = 960: the persistent z pass on the radix-16-based plan does
+    # not fit in LDS, so variant 4 runs the wave-owned pass (the same kernel
+    # as variant 1); variant 3 runs the radix-32-based plan's persistent form,
+    # which fits, and agrees to rounding
     n = 480
     rho = inputs.make_density(n, 6, 4800, sigma=(0.02, 0.06), noise=1e-3)
     s = S.Solver(n, 1.0 / n, "f64")
     r = torch.from_numpy(rho).to("cuda", torch.float64)
     S.ps_plan_set_variant(s.plan, 2, 1)
+    S.ps_plan_set_variant(s.plan, 6, 0)
     ref = s(r)
-    for zmode in (3, 4):
-        S.ps_plan_set_variant(s.plan, 2, zmode)
-        assert torch.equal(s(r), ref), zmode
+    S.ps_plan_set_variant(s.plan, 2, 4)
+    assert torch.equal(s(r), ref)
+    S.ps_plan_set_variant(s.plan, 2, 3)
+    err = float((s(r) - ref).norm() / ref.norm())
+    assert err <= 1e-13, err
 
 
 def test_autotune_writes_cache(tmp_path):
