@@ -208,9 +208,9 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
                            void *stream);
 
 /* Choose the kernel variant of one pass of a pruned plan (host only, no HIP
- * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = radix-32-
- * based plan (two stages; n = 256, 320, 384, 480 and 512 only); passes 1 and
- * 3 (the y passes) also
+ * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = two-stage
+ * plan, radix 32 or 24 first (n = 144, 160, 192, 240, 256, 288, 320, 360,
+ * 384, 480 and 512 only); passes 1 and 3 (the y passes) also
  * take 2 and 3, the same plans run by persistent workgroups that load the
  * next tile while transforming the current one, and 4 and 5, the plans of 0
  * and 1 with half as many pencils per workgroup (8 in float, 4 in double:
@@ -219,13 +219,13 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * 16) and 4 and 5 (32 rows, where the LDS holds them; PS_ERR_UNSUPPORTED
  * otherwise), the family again in the low bit.  Pass 2 (the fused z pass): 0 =
  * workgroup-synchronised pencils, 1 = wavefront-owned pencils, 2 =
- * wavefront-owned pencils on the radix-32-based plan (n = 256, 320, 384,
- * 480, 512; else as 1), 3 = persistent workgroups that load the next tile while
- * transforming the current one (radix-32-based plan where it exists, else
+ * wavefront-owned pencils on the two-stage plan (where it exists; else as
+ * 1), 3 = persistent workgroups that load the next tile while
+ * transforming the current one (two-stage plan where it exists, else
  * radix-16-based), 4 = persistent on the radix-16-based plan with fewer
  * pencils per wavefront.  Boxes (ps_plan_create_box with unequal lengths)
  * run the one-tile-per-workgroup variants only: y passes 0 and 1, z pass 0,
- * 1 and 2 (PS_ERR_UNSUPPORTED otherwise); the radix-32-based plan follows
+ * 1 and 2 (PS_ERR_UNSUPPORTED otherwise); the two-stage plan follows
  * the length of the axis the pass transforms.  Every variant computes the
  * same result to rounding.  PS_F32_SPLIT plans keep the radix-16-based plan
  * (no variant 1 of passes 0, 1, 3, 4, no z variant 2); for them "pass" 5 sets the

@@ -69,17 +69,31 @@ hipError_t green_run(const GreenBufs& b)
 
 template <class RP> static void rlist(std::vector<int>& v) { v.assign(RP::r, RP::r + RP::S); }
 
-bool has_family1(int P) { return P == 512 || P == 640 || P == 768 || P == 960 || P == 1024; }
+bool has_family1(int P)
+{
+    switch (P) {
+#define PS_CASE(PP) \
+    case PP: return has_fam1<PP>();
+        PS_FOR_EACH_P(PS_CASE)
+#undef PS_CASE
+    default: return false;
+    }
+}
+
+template <int P> static void rlist1(std::vector<int>& fwd)
+{
+    if constexpr (has_fam1<P>()) rlist<typename PlanFor<P, 1>::Fwd>(fwd);
+}
 
 bool host_radices(int P, std::vector<int>& fwd, int fam)
 {
     if (fam == 1 && has_family1(P)) {
         switch (P) {
-        case 512: rlist<PlanFor<512, 1>::Fwd>(fwd); break;
-        case 640: rlist<PlanFor<640, 1>::Fwd>(fwd); break;
-        case 768: rlist<PlanFor<768, 1>::Fwd>(fwd); break;
-        case 960: rlist<PlanFor<960, 1>::Fwd>(fwd); break;
-        default: rlist<PlanFor<1024, 1>::Fwd>(fwd); break;
+#define PS_CASE(PP) \
+    case PP: rlist1<PP>(fwd); break;
+            PS_FOR_EACH_P(PS_CASE)
+#undef PS_CASE
+        default: break;
         }
         return true;
     }

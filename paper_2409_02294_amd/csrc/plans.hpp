@@ -50,19 +50,37 @@ template <> struct PlanFor<960, 0> { using Fwd = Radices<16, 15, 4>; using Inv =
     X(16) X(32) X(48) X(64) X(80) X(96) X(128) X(144) X(160) X(192) X(240) X(256) X(288) X(320) X(384)    \
     X(400) X(432) X(480) X(512) X(576) X(640) X(720) X(768) X(800) X(864) X(960) X(1024)
 
-// Family 1: radix 32 first and two stages in all (one LDS exchange fewer per
-// transform than family 0) where P allows it; 20, 24 and 30 are prime-factor
-// DFTs in registers.
-template <int P> constexpr bool has_fam1() { return P == 512 || P == 640 || P == 768 || P == 960 || P == 1024; }
+// Family 1: two stages in all (one LDS exchange fewer per transform than
+// family 0 where that has three or more), radix 32 first where P allows it,
+// else radix 24; 10, 12, 15, 20, 24 and 30 are prime-factor DFTs in registers.
+template <int P> constexpr bool has_fam1()
+{
+    return P == 288 || P == 320 || P == 384 || P == 480 || P == 512 || P == 576 || P == 640 || P == 720 ||
+           P == 768 || P == 960 || P == 1024;
+}
+template <> struct PlanFor<288, 1> { using Fwd = Radices<24, 12>; using Inv = Radices<12, 24>; };
+template <> struct PlanFor<320, 1> { using Fwd = Radices<32, 10>; using Inv = Radices<10, 32>; };
+template <> struct PlanFor<384, 1> { using Fwd = Radices<32, 12>; using Inv = Radices<12, 32>; };
+template <> struct PlanFor<480, 1> { using Fwd = Radices<32, 15>; using Inv = Radices<15, 32>; };
 template <> struct PlanFor<512, 1> { using Fwd = Radices<32, 16>; using Inv = Radices<16, 32>; };
+template <> struct PlanFor<576, 1> { using Fwd = Radices<24, 24>; using Inv = Radices<24, 24>; };
 template <> struct PlanFor<640, 1> { using Fwd = Radices<32, 20>; using Inv = Radices<20, 32>; };
+template <> struct PlanFor<720, 1> { using Fwd = Radices<24, 30>; using Inv = Radices<30, 24>; };
 template <> struct PlanFor<768, 1> { using Fwd = Radices<32, 24>; using Inv = Radices<24, 32>; };
 template <> struct PlanFor<960, 1> { using Fwd = Radices<32, 30>; using Inv = Radices<30, 32>; };
 template <> struct PlanFor<1024, 1> { using Fwd = Radices<32, 32>; using Inv = Radices<32, 32>; };
 // Elements per thread of a family-1 pass: 32 where both radices are powers
 // of two (a thread may hold two radix-16 butterflies), else the smaller
 // radix, so that the stage with the most butterflies gives each thread one.
-template <int P> constexpr int fam1_elems() { return P == 640 ? 20 : P == 768 ? 24 : P == 960 ? 30 : 32; }
+template <int P> constexpr int fam1_elems()
+{
+    if constexpr (!has_fam1<P>() || P == 512 || P == 1024) {
+        return 32;
+    } else {
+        using R = typename PlanFor<P, 1>::Fwd;
+        return R::r[0] < R::r[1] ? R::r[0] : R::r[1];
+    }
+}
 
 // Threads for B pencils of length P at ~E elements per thread, whole waves.
 constexpr int threads_for(int B, int P, int E = 16)

@@ -453,16 +453,16 @@ const ZDefault Z_DEFAULTS[] = {
     { 192, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
     { 240, {1, 1, 4}, {1, 1, 1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
     { 256, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
-    { 288, {0, 0, 1}, {0, 1, 1}, {2, 2, 4}, {-1, 2, 4}, {-1, -1, -1}, {-1, -1, -1}},
-    { 320, {0, 0, 0}, {0, 1, 1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
-    { 384, {0, 0, 0}, {0, 1, 1}, {-1, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 288, {0, 0, 1}, {0, 1, 1}, {2, 2, 4}, {1, 2, 4}, {-1, 5, -1}, {5, 5, -1}},
+    { 320, {0, 0, 0}, {0, 1, 1}, {2, 2, -1}, {-1, -1, -1}, {-1, 4, -1}, {-1, 4, -1}},
+    { 384, {0, 0, 0}, {0, 1, 1}, {-1, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, 4, -1}},
     { 400, {4, 4, 1}, {0, 1, 0}, {2, 2, 2}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, -1}},
     { 432, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
-    { 480, {1, 1, 1}, {0, 0, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, -1, -1}, {-1, -1, -1}},
+    { 480, {3, 2, 1}, {1, 1, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {-1, 5, -1}},
     { 512, {4, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
-    { 576, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}, {2, 4, 4}, {4, 4, -1}},
+    { 576, {2, 2, 1}, {0, 0, 0}, {2, 1, -1}, {2, 1, 2}, {1, 1, 4}, {1, 5, -1}},
     { 640, {1, 2, 1}, {1, 1, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
-    { 720, {0, 1, 1}, {1, 0, 0}, {2, -1, -1}, {2, 2, 2}, {-1, 4, 4}, {4, 4, 4}},
+    { 720, {0, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 2, 2}, {1, 4, 4}, {4, 5, 4}},
     { 768, {0, 2, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 1, -1}, {-1, -1, 4}},
     { 800, {4, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {4, 4, 4}},
     { 864, {1, 4, 1}, {0, 1, 0}, {2, -1, -1}, {2, 2, 2}, {2, 4, -1}, {-1, -1, 4}},

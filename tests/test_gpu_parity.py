@@ -362,11 +362,13 @@ def test_zmodes_match_oracle(prec, n, zmode, ztile):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("n", [320, 384, 480])
+@pytest.mark.parametrize("n", [144, 160, 192, 240, 288, 320, 360, 384, 480])
 def test_two_stage_radix32_family(prec, n):
-    # P = 640, 768, 960 as radix 32 by a prime-factor radix (20, 24, 30):
-    # every variant on that family agrees with the radix-16-based plan to
-    # rounding, and the solve matches direct sums at sampled cells
+    # the two-stage plans (P = 288: 24 x 12, 320: 32 x 10, 384: 32 x 12,
+    # 480: 32 x 15, 576: 24 x 24, 640: 32 x 20, 720: 24 x 30, 768: 32 x 24,
+    # 960: 32 x 30): every variant on that family agrees with the
+    # radix-16-based plan to rounding, and the solve matches direct sums at
+    # sampled cells
     rho_np = inputs.make_density(n, 12, 800 + n, sigma=(0.02, 0.06), noise=1e-3)
     s = S.Solver(n, 1.0 / n, prec)
     rho = torch.from_numpy(rho_np).to("cuda", _dtype(prec))
