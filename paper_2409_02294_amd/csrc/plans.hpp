@@ -52,11 +52,12 @@ template <> struct PlanFor<960, 0> { using Fwd = Radices<16, 15, 4>; using Inv =
 
 // Family 1: two stages in all (one LDS exchange fewer per transform than
 // family 0 where that has three or more), radix 32 first where P allows it,
-// else radix 24; 10, 12, 15, 20, 24 and 30 are prime-factor DFTs in registers.
+// else radix 24; 10, 12, 15, 20, 24 and 30 are prime-factor DFTs in
+// registers, 25 and 27 Cooley-Tukey ones (5 x 5, 3 x 9).
 template <int P> constexpr bool has_fam1()
 {
     return P == 288 || P == 320 || P == 384 || P == 480 || P == 512 || P == 576 || P == 640 || P == 720 ||
-           P == 768 || P == 960 || P == 1024;
+           P == 768 || P == 800 || P == 864 || P == 960 || P == 1024;
 }
 template <> struct PlanFor<288, 1> { using Fwd = Radices<24, 12>; using Inv = Radices<12, 24>; };
 template <> struct PlanFor<320, 1> { using Fwd = Radices<32, 10>; using Inv = Radices<10, 32>; };
@@ -67,6 +68,8 @@ template <> struct PlanFor<576, 1> { using Fwd = Radices<24, 24>; using Inv = Ra
 template <> struct PlanFor<640, 1> { using Fwd = Radices<32, 20>; using Inv = Radices<20, 32>; };
 template <> struct PlanFor<720, 1> { using Fwd = Radices<24, 30>; using Inv = Radices<30, 24>; };
 template <> struct PlanFor<768, 1> { using Fwd = Radices<32, 24>; using Inv = Radices<24, 32>; };
+template <> struct PlanFor<800, 1> { using Fwd = Radices<32, 25>; using Inv = Radices<25, 32>; };
+template <> struct PlanFor<864, 1> { using Fwd = Radices<32, 27>; using Inv = Radices<27, 32>; };
 template <> struct PlanFor<960, 1> { using Fwd = Radices<32, 30>; using Inv = Radices<30, 32>; };
 template <> struct PlanFor<1024, 1> { using Fwd = Radices<32, 32>; using Inv = Radices<32, 32>; };
 // Elements per thread of a family-1 pass: 32 where both radices are powers

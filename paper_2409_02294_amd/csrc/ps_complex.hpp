@@ -6,6 +6,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace ps {
 
 template <typename T> struct cx_of;
@@ -233,6 +235,92 @@ template <int DIR, typename V> __device__ __forceinline__ void dft32(V* v)
 
 template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v);
 
+// Compile-time cos and sin of the angle 2 pi m / n (double precision,
+// rounded once to T where used): the angle is folded into [0, pi/2] by the
+// symmetries of sin and cos and summed as Taylor series.  The twiddles of
+// in-register DFTs whose length is not covered by the constants above.
+constexpr double ct_pi = 3.14159265358979323846264338327950288;
+constexpr double ct_sin_series(double x)
+{
+    double term = x, sum = x;
+    for (int k = 1; k < 20; ++k) {
+        term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double ct_cos_series(double x)
+{
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 20; ++k) {
+        term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+// m in (-n/2, n/2]: angle 2 pi m / n in (-pi, pi]
+constexpr int ct_fold(int m, int n)
+{
+    m %= n;
+    if (m < 0) m += n;
+    if (2 * m > n) m -= n;
+    return m;
+}
+constexpr double ct_cos_2pi(int m, int n)
+{
+    const int a = ct_fold(m, n) < 0 ? -ct_fold(m, n) : ct_fold(m, n);  // cos is even
+    // angle 2 pi a / n in [0, pi]; beyond pi/2 use cos(x) = -cos(pi - x)
+    return 4 * a <= n ? ct_cos_series(2.0 * ct_pi * a / n) : -ct_cos_series(ct_pi * (n - 2 * a) / n);
+}
+constexpr double ct_sin_2pi(int m, int n)
+{
+    const int f = ct_fold(m, n), a = f < 0 ? -f : f;
+    const double v = 4 * a <= n ? ct_sin_series(2.0 * ct_pi * a / n) : ct_sin_series(ct_pi * (n - 2 * a) / n);
+    return f < 0 ? -v : v;  // sin is odd; sin(x) = sin(pi - x)
+}
+template <int I, int N, class F> __device__ __forceinline__ void ct_loop(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        ct_loop<I + 1, N>(f);
+    }
+}
+
+// Cooley-Tukey DFT of length N1 N2 in registers, for factors that share a
+// prime (9 = 3 x 3, 25 = 5 x 5, 27 = 3 x 9): n = N2 n1 + n2, k = k1 + N1 k2;
+// N2 DFTs of length N1 along n1, the twiddles w^(n2 k1) (w = exp(DIR 2 pi i
+// / N1 N2)), then N1 DFTs of length N2 along n2.
+template <int DIR, int N1, int N2, typename V> __device__ __forceinline__ void dft_ct(V* v)
+{
+    using T = decltype(v[0].x);
+    constexpr int N = N1 * N2;
+    V a[N2][N1];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2)
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) a[n2][n1] = v[N2 * n1 + n2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) dft<N1, DIR>(a[n2]);
+    ct_loop<1, N2>([&](auto i2) {
+        constexpr int n2 = decltype(i2)::value;
+        ct_loop<1, N1>([&](auto i1) {
+            constexpr int k1 = decltype(i1)::value;
+            constexpr double c = ct_cos_2pi(n2 * k1, N), sn = DIR * ct_sin_2pi(n2 * k1, N);
+            V& x = a[n2][k1];
+            x = V{x.x * T(c) - x.y * T(sn), x.x * T(sn) + x.y * T(c)};
+        });
+    });
+    V b[N2];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) b[n2] = a[n2][k1];
+        dft<N2, DIR>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) v[k1 + N1 * k2] = b[k2];
+    }
+}
+
 // Prime-factor (Good-Thomas) DFT of length N1 N2 with gcd(N1, N2) = 1: no
 // twiddle factors.  Inputs are read at j = (N2 j1 + N1 j2) mod N into an
 // N1 x N2 array, N2 DFTs of length N1 run along j1 and N1 DFTs of length N2
@@ -284,6 +372,9 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft(V* v)
     else if constexpr (R == 20) dft_pfa<DIR, 4, 5>(v);
     else if constexpr (R == 24) dft_pfa<DIR, 8, 3>(v);
     else if constexpr (R == 30) dft_pfa<DIR, 2, 15>(v);
+    else if constexpr (R == 9) dft_ct<DIR, 3, 3>(v);
+    else if constexpr (R == 25) dft_ct<DIR, 5, 5>(v);
+    else if constexpr (R == 27) dft_ct<DIR, 3, 9>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
     else if constexpr (R == 32) dft32<DIR>(v);

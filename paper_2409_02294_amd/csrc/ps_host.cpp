@@ -464,8 +464,8 @@ const ZDefault Z_DEFAULTS[] = {
     { 640, {1, 2, 1}, {1, 1, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
     { 720, {0, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 2, 2}, {1, 4, 4}, {4, 5, 4}},
     { 768, {0, 2, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 1, -1}, {-1, -1, 4}},
-    { 800, {4, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {4, 4, 4}},
-    { 864, {1, 4, 1}, {0, 1, 0}, {2, -1, -1}, {2, 2, 2}, {2, 4, -1}, {-1, -1, 4}},
+    { 800, {2, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 3, 2}, {1, 1, -1}, {4, 5, 4}},
+    { 864, {3, 2, 1}, {0, 0, 0}, {3, 1, -1}, {3, 3, 2}, {1, 1, -1}, {5, 5, 4}},
     { 960, {2, 2, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {-1, 4, 4}},
     {1024, {2, 3, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, 4}},
 };
