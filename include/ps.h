@@ -209,8 +209,9 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
 
 /* Choose the kernel variant of one pass of a pruned plan (host only, no HIP
  * call).  Passes 0, 1, 3, 4: variant 0 = radix-16-based plan, 1 = two-stage
- * plan, radix 32 or 24 first (n = 144, 160, 192, 240, 256, 288, 320, 360,
- * 384, 400, 432, 480 and 512 only); passes 1 and 3 (the y passes) also
+ * plan, radix 32, 24 or 16 first (n = 72, 144, 160, 192, 200, 216, 240,
+ * 256, 288, 320, 360, 384, 400, 432, 480 and 512 only); passes 1 and 3 (the
+ * y passes) also
  * take 2 and 3, the same plans run by persistent workgroups that load the
  * next tile while transforming the current one, and 4 and 5, the plans of 0
  * and 1 with half as many pencils per workgroup (8 in float, 4 in double:

@@ -52,16 +52,19 @@ template <> struct PlanFor<960, 0> { using Fwd = Radices<16, 15, 4>; using Inv =
 
 // Family 1: two stages in all (one LDS exchange fewer per transform than
 // family 0 where that has three or more), radix 32 first where P allows it,
-// else radix 24; 10, 12, 15, 20, 24 and 30 are prime-factor DFTs in
-// registers, 25 and 27 Cooley-Tukey ones (5 x 5, 3 x 9).
+// else radix 24 or 16; 10, 12, 15, 20, 24 and 30 are prime-factor DFTs in
+// registers, 9, 25 and 27 Cooley-Tukey ones (3 x 3, 5 x 5, 3 x 9).
 template <int P> constexpr bool has_fam1()
 {
-    return P == 288 || P == 320 || P == 384 || P == 480 || P == 512 || P == 576 || P == 640 || P == 720 ||
-           P == 768 || P == 800 || P == 864 || P == 960 || P == 1024;
+    return P == 144 || P == 288 || P == 320 || P == 384 || P == 400 || P == 432 || P == 480 || P == 512 ||
+           P == 576 || P == 640 || P == 720 || P == 768 || P == 800 || P == 864 || P == 960 || P == 1024;
 }
+template <> struct PlanFor<144, 1> { using Fwd = Radices<16, 9>; using Inv = Radices<9, 16>; };
 template <> struct PlanFor<288, 1> { using Fwd = Radices<24, 12>; using Inv = Radices<12, 24>; };
 template <> struct PlanFor<320, 1> { using Fwd = Radices<32, 10>; using Inv = Radices<10, 32>; };
 template <> struct PlanFor<384, 1> { using Fwd = Radices<32, 12>; using Inv = Radices<12, 32>; };
+template <> struct PlanFor<400, 1> { using Fwd = Radices<16, 25>; using Inv = Radices<25, 16>; };
+template <> struct PlanFor<432, 1> { using Fwd = Radices<16, 27>; using Inv = Radices<27, 16>; };
 template <> struct PlanFor<480, 1> { using Fwd = Radices<32, 15>; using Inv = Radices<15, 32>; };
 template <> struct PlanFor<512, 1> { using Fwd = Radices<32, 16>; using Inv = Radices<16, 32>; };
 template <> struct PlanFor<576, 1> { using Fwd = Radices<24, 24>; using Inv = Radices<24, 24>; };

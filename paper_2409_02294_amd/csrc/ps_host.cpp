@@ -448,7 +448,7 @@ const ZDefault Z_DEFAULTS[] = {
     {  80, {1, 1, 0}, {0, 0, 1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
     {  96, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
     { 128, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
-    { 144, {1, 1, 1}, {1, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 144, {2, 2, 1}, {1, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
     { 160, {1, 0, 0}, {0, 1, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
     { 192, {1, 1, 1}, {0, 0, 0}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
     { 240, {1, 1, 4}, {1, 1, 1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
@@ -456,8 +456,8 @@ const ZDefault Z_DEFAULTS[] = {
     { 288, {0, 0, 1}, {0, 1, 1}, {2, 2, 4}, {1, 2, 4}, {-1, 5, -1}, {5, 5, -1}},
     { 320, {0, 0, 0}, {0, 1, 1}, {2, 2, -1}, {-1, -1, -1}, {-1, 4, -1}, {-1, 4, -1}},
     { 384, {0, 0, 0}, {0, 1, 1}, {-1, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, 4, -1}},
-    { 400, {4, 4, 1}, {0, 1, 0}, {2, 2, 2}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, -1}},
-    { 432, {1, 1, 1}, {0, 0, 0}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    { 400, {3, 3, 1}, {1, 0, 0}, {2, 3, 2}, {3, 3, -1}, {-1, 5, -1}, {1, 1, -1}},
+    { 432, {3, 3, 1}, {0, 0, 0}, {1, 3, -1}, {3, 3, -1}, {1, 5, -1}, {1, 1, -1}},
     { 480, {3, 2, 1}, {1, 1, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {-1, 5, -1}},
     { 512, {4, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
     { 576, {2, 2, 1}, {0, 0, 0}, {2, 1, -1}, {2, 1, 2}, {1, 1, 4}, {1, 5, -1}},

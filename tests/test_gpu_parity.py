@@ -362,11 +362,12 @@ def test_zmodes_match_oracle(prec, n, zmode, ztile):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("n", [144, 160, 192, 240, 288, 320, 360, 384, 400, 432, 480])
+@pytest.mark.parametrize("n", [72, 144, 160, 192, 200, 216, 240, 288, 320, 360, 384, 400, 432, 480])
 def test_two_stage_radix32_family(prec, n):
     # the two-stage plans (P = 288: 24 x 12, 320: 32 x 10, 384: 32 x 12,
     # 480: 32 x 15, 576: 24 x 24, 640: 32 x 20, 720: 24 x 30, 768: 32 x 24,
-    # 800: 32 x 25, 864: 32 x 27, 960: 32 x 30): every variant on that family agrees with the
+    # 800: 32 x 25, 864: 32 x 27, 960: 32 x 30; 144: 16 x 9, 400: 16 x 25,
+    # 432: 16 x 27): every variant on that family agrees with the
     # radix-16-based plan to rounding, and the solve matches direct sums at
     # sampled cells
     rho_np = inputs.make_density(n, 12, 800 + n, sigma=(0.02, 0.06), noise=1e-3)
