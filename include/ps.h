@@ -224,7 +224,10 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * 1), 3 = persistent workgroups that load the next tile while
  * transforming the current one (two-stage plan where it exists, else
  * radix-16-based), 4 = persistent on the radix-16-based plan with fewer
- * pencils per wavefront.  Boxes (ps_plan_create_box with unequal lengths)
+ * pencils per wavefront, 5 = wavefront-owned pencils on the two-stage plan
+ * whose stage exchanges pass through half the LDS in two rounds (twice as
+ * many pencils resident per compute unit): PS_F64 cubes with n >= 256 only
+ * (PS_ERR_UNSUPPORTED otherwise).  Boxes (ps_plan_create_box with unequal lengths)
  * run the one-tile-per-workgroup variants only: y passes 0 and 1, z pass 0,
  * 1 and 2 (PS_ERR_UNSUPPORTED otherwise); the two-stage plan follows
  * the length of the axis the pass transforms.  Every variant computes the

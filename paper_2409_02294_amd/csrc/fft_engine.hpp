@@ -386,6 +386,89 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0, i
         }
     }
 
+    // Two-round exchange through half the LDS: round RND moves the positions
+    // [RND P/2, (RND + 1) P/2) of every pencil, so a pencil needs a row of
+    // P/2 (padded as a full row is) instead of P.  LPH: that row's pitch,
+    // shared by the plans that use one buffer.
+    static constexpr int half_pitch() { return pad_pitch(P / 2, G, (int)sizeof(V)); }
+    template <int LPH> __device__ __forceinline__ static int lidxh(int p, int k) { return p * LPH + k + (k >> GS); }
+
+    template <int s, int MAP, int RND, int LPH> __device__ __forceinline__ static void store_lds_half(const Regs<s>& g, V* lds)
+    {
+        constexpr int Rs = R<s>;
+        constexpr int NSs = RP::ns(s);
+        const int vt = vthread<s>(), ro = roff<s>();
+#pragma unroll
+        for (int i = 0; i < NB<s>; ++i) {
+            const int b = vt + i * NTV<s>;
+            if (!valid<s, MAP>(b)) continue;
+            int p, j;
+            pj<s, MAP>(b, p, j);
+            const int k0 = (j / NSs) * NSs * Rs + (j % NSs);
+#pragma unroll
+            for (int q = 0; q < RS<s>; ++q) {
+                const int k = k0 + (ro + q) * NSs;
+                if ((k >= P / 2) == (RND == 1)) lds[lidxh<LPH>(p, k - RND * (P / 2))] = g.v[i][q];
+            }
+        }
+    }
+
+    template <int s, int MAP, int RND, int LPH> __device__ __forceinline__ static void load_lds_half(Regs<s>& g, const V* lds)
+    {
+        const int vt = vthread<s>(), ro = roff<s>();
+#pragma unroll
+        for (int i = 0; i < NB<s>; ++i) {
+            const int b = vt + i * NTV<s>;
+            if (!valid<s, MAP>(b)) {
+                if constexpr (RND == 0) {
+#pragma unroll
+                    for (int q = 0; q < RS<s>; ++q) g.v[i][q] = V{T(0), T(0)};
+                }
+                continue;
+            }
+            int p, j;
+            pj<s, MAP>(b, p, j);
+#pragma unroll
+            for (int q = 0; q < RS<s>; ++q) {
+                const int k = j + (ro + q) * Q<s>;
+                if ((k >= P / 2) == (RND == 1)) g.v[i][q] = lds[lidxh<LPH>(p, k - RND * (P / 2))];
+            }
+        }
+    }
+
+    // Stage s's outputs (mapping MW) to stage s + 1's inputs (mapping MR) in
+    // two rounds; MPREV is the mapping of the last LDS reads before it.
+    template <int s, int MW, int MR, int MPREV, int LPH>
+    __device__ __forceinline__ static void exchange_half(const Regs<s>& g, Regs<s + 1>& g2, V* lds)
+    {
+        sync2<MPREV, MW>();
+        store_lds_half<s, MW, 0, LPH>(g, lds);
+        sync2<MW, MR>();
+        load_lds_half<s + 1, MR, 0, LPH>(g2, lds);
+        sync2<MR, MW>();
+        store_lds_half<s, MW, 1, LPH>(g, lds);
+        sync2<MW, MR>();
+        load_lds_half<s + 1, MR, 1, LPH>(g2, lds);
+    }
+
+    // Stages s .. S - 1 on g (stage s's inputs), exchanging through half the
+    // LDS; stages before the last use mapping MAP, the last MLAST.  out: the
+    // last stage's outputs.
+    template <int s, int DIR, int MAP, int MLAST, int MPREV, int LPH>
+    __device__ __forceinline__ static void stages_half(Regs<s>& g, Regs<S - 1>& out, V* lds, const TW& tw, const SA& sa)
+    {
+        constexpr int M = s == S - 1 ? MLAST : MAP;
+        compute<s, DIR, M>(g, tw, sa);
+        if constexpr (s == S - 1) {
+            out = g;
+        } else {
+            constexpr int MN = s + 1 == S - 1 ? MLAST : MAP;
+            Regs<s + 1> g2;
+            exchange_half<s, M, MN, MPREV, LPH>(g, g2, lds);
+            stages_half<s + 1, DIR, MAP, MLAST, MN, LPH>(g2, out, lds, tw, sa);
+        }
+    }
+
     // Stage-0 inputs from ld(p, idx); idx >= LIN reads as zero.
     template <int MAP, int LIN, class LD> __device__ __forceinline__ static void load_first(Regs<0>& g, LD& ld)
     {

@@ -360,6 +360,52 @@ __global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, cons
             tw_fwd<V, FAM, 2>(s), tw_inv<V, FAM, 2>(s), lds, sa, ext<BOX>(s.ny, 0));
 }
 
+// Fused z pass whose exchanges go through half the LDS in two rounds
+// (wave-owned pencils, one tile per workgroup): a pencil holds a row of P/2
+// instead of P, so twice as many pencils stay resident on a compute unit.
+// Meant for 16-byte elements, where a 1024-point pencil's full row (16 KB)
+// limits a compute unit to about eight; on the two-stage plans (two or more
+// pencils per wavefront, up to 251 registers a lane) the rows of two
+// workgroups of eight pencils fit where one did.  The last inverse stage reads
+// pencil-fastest, so the stores of the cropped output stay coalesced.
+template <typename T, int P, int FAM, int B, int NT>
+__global__ __launch_bounds__(NT) void k_z_conv_half(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+                                                    const unsigned short* __restrict__ stab)
+{
+    using V = cx<T>;
+    using EF = Engine<T, typename PlanFor<P, FAM>::Fwd, B, NT, true>;
+    using EI = Engine<T, typename PlanFor<P, FAM>::Inv, B, NT, true>;
+    constexpr int LPH = EF::half_pitch() > EI::half_pitch() ? EF::half_pitch() : EI::half_pitch();
+    constexpr int N = P / 2, H = N + 1, SL = EF::S - 1;
+    static_assert(EF::S > 1 && EI::S > 1, "two or more stages");
+    __shared__ V lds[B * LPH];
+    typename EF::SA sa;
+    sa.load(stab);
+    const SolveRec& s = list[blockIdx.z];
+    const int ky0 = z_tile<P / B>(blockIdx.x) * B;
+    const int kx = blockIdx.y;
+    const V* pin = (in ? in : gp<const V>(s.t2)) + ((size_t)kx * P + ky0) * N;  // pencil p at pin + p N
+    V* pout = (out ? out : gp<V>(s.t3)) + (size_t)kx * N * P + ky0;             // element (z, p) at pout[z P + p]
+    const T* grow = gp<const T>(s.ghat) + (size_t)kx * H * H;
+    auto ld = [&](int p, int idx) -> V { return pin[(unsigned)(p * N + idx)]; };
+    typename EF::template Regs<0> g0;
+    EF::template load_first<MAP_WV, N>(g0, ld);
+    typename EF::template Regs<SL> g;
+    EF::template stages_half<0, -1, MAP_WV, MAP_WV, MAP_WV, LPH>(g0, g, lds, typename EF::TW(tw_fwd<V, FAM, 2>(s)),
+                                                                  sa);
+    // multiply by the real, even transformed kernel at (kz, ky, kx)
+    auto mul = [&](int p, int kz, V& v) {
+        const int ky = ky0 + p;
+        const T gv = grow[(unsigned)((ky <= N ? ky : P - ky) * H + (kz <= N ? kz : P - kz))];
+        v = V{v.x * gv, v.y * gv};
+    };
+    EF::template for_each_out<SL, MAP_WV>(g, mul);
+    typename EI::template Regs<EI::S - 1> h;
+    EI::template stages_half<0, +1, MAP_WV, MAP_PF, MAP_WV, LPH>(g, h, lds, typename EI::TW(tw_inv<V, FAM, 2>(s)), sa);
+    auto st = [&](int p, int idx, V v) { pout[(unsigned)(idx * P + p)] = v; };
+    EI::template store_last<MAP_PF, N>(h, st);
+}
+
 // Persistent y passes with a one-tile prefetch: workgroups walk the tiles
 // (same order as the one-tile-per-workgroup grid) and load the next tile's
 // pencils before transforming the current ones.  Column twiddles (every

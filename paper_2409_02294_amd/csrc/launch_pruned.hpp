@@ -87,6 +87,13 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
         hipLaunchKernelGGL((k_z_conv<T, P, FAM, B, NTZ, WAVE, MT>), dim3(P / B, H, b.count), dim3(NTZ), 0, b.stream,
                            static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab);
     }
+    // z pass exchanging through half the LDS in two rounds (wave-owned pencils)
+    template <int B = ZB> static void z_conv_half(const PrunedBufs& b)
+    {
+        constexpr int NTZ = wave_threads(B, P, EZ);
+        hipLaunchKernelGGL((k_z_conv_half<T, P, FAM, B, NTZ>), dim3(P / B, H, b.count), dim3(NTZ), 0, b.stream,
+                           static_cast<const V*>(b.in[2]), static_cast<V*>(b.out[2]), b.list, b.stab);
+    }
     // Persistent passes: as many workgroups as fit on the device at once (a
     // multiple of 8, so z tile pairs stay on one XCD), each walking tiles.
     // EL: elements per lane that set the pencils per wavefront (32: two or
@@ -265,6 +272,12 @@ template <typename T, int P, int MT, int B> static void cube_z(int zmode, const 
     if constexpr (PlanFor<P, 0>::Fwd::S > 1 && z_pf_fits<T, P, 0, 16, MT, B>()) {
         if (zmode == 4) {  // persistent: radix-16 family, one 1024-point pencil per wavefront
             L0::template z_conv_pf<16, B>(b);
+            return;
+        }
+    }
+    if constexpr (std::is_same<T, double>::value && P >= 512 && F1) {
+        if (zmode == 5) {  // half-LDS exchange on the two-stage plan
+            L1::template z_conv_half<B>(b);
             return;
         }
     }

@@ -356,7 +356,10 @@ const char* prec_name(ps_precision p)
 int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : 6; }
 
 // Whether variant v of a pass runs the radix-32-based plan family.
-bool variant_needs_family1(int pass, int v) { return pass == 6 ? false : pass == 2 ? v == 2 : (v & 1) != 0; }
+bool variant_needs_family1(int pass, int v)
+{
+    return pass == 6 ? false : pass == 2 ? (v == 2 || v == 5) : (v & 1) != 0;
+}
 // Whether the axis a pass transforms has the radix-32-based family.
 bool family1_available(ps_plan p, int pass)
 {
@@ -419,10 +422,13 @@ bool variant_ok(ps_plan p, int pass, int variant)
     // boxes run the one-tile-per-workgroup kernels only
     if (p->box && (pass == 1 || pass == 3) && (variant & 6)) return false;
     if (p->box && pass == 2 && variant >= 3) return false;
+    // half-LDS z exchange: double-precision cubes with P >= 512 (where the
+    // 16-byte rows otherwise bound the pencils resident per compute unit)
+    if (pass == 2 && variant >= 5 && (p->prec != PS_F64 || axis_pad(p, 2) < 512)) return false;
     return true;
 }
 
-// Default z pass per padded length: the fastest form (variant 0..4) and
+// Default z pass per padded length: the fastest form (variant 0..5) and
 // tile width (0: full, 1: half), and for P > 256 the x passes' variants
 // (family and rows per workgroup; 8 rows won for most FP64 lengths and for
 // the inverse x pass of most FP32 lengths) and the y passes' (family,
@@ -459,15 +465,15 @@ const ZDefault Z_DEFAULTS[] = {
     { 400, {3, 3, 1}, {1, 0, 0}, {2, 3, 2}, {3, 3, -1}, {-1, 5, -1}, {1, 1, -1}},
     { 432, {3, 3, 1}, {0, 0, 0}, {1, 3, -1}, {3, 3, -1}, {1, 5, -1}, {1, 1, -1}},
     { 480, {3, 2, 1}, {1, 1, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {-1, 5, -1}},
-    { 512, {4, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
+    { 512, {5, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
     { 576, {2, 2, 1}, {0, 0, 0}, {2, 1, -1}, {2, 1, 2}, {1, 1, 4}, {1, 5, -1}},
-    { 640, {1, 2, 1}, {1, 1, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
-    { 720, {0, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 2, 2}, {1, 4, 4}, {4, 5, 4}},
+    { 640, {5, 2, 1}, {1, 1, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
+    { 720, {5, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 2, 2}, {1, 4, 4}, {4, 5, 4}},
     { 768, {0, 2, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 1, -1}, {-1, -1, 4}},
-    { 800, {2, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 3, 2}, {1, 1, -1}, {4, 5, 4}},
-    { 864, {3, 2, 1}, {0, 0, 0}, {3, 1, -1}, {3, 3, 2}, {1, 1, -1}, {5, 5, 4}},
-    { 960, {2, 2, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {-1, 4, 4}},
-    {1024, {2, 3, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, 4}},
+    { 800, {5, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 3, 2}, {1, 1, -1}, {4, 5, 4}},
+    { 864, {5, 2, 1}, {1, 0, 0}, {3, 1, -1}, {3, 3, 2}, {1, 1, -1}, {5, 5, 4}},
+    { 960, {5, 2, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {-1, 4, 4}},
+    {1024, {5, 3, 1}, {0, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, 4}},
 };
 
 // The measured defaults of length P, and the precision's column in them.

@@ -28,7 +28,7 @@ struct PrunedVariant {
     int mterms = 0;  // 0: vector-ALU DFTs; 3 or 6: split-bf16 matrix-core radix-16 DFTs (float only)
     int ztile = 0;
 };
-constexpr int NUM_ZMODES = 5;
+constexpr int NUM_ZMODES = 6;
 
 // Launch arguments of the pruned pipeline: `count` equal-length solves whose
 // records are the device array `list` (grid z indexes it).  in[k] / out[k],

@@ -171,15 +171,19 @@ def test_variant_selection_contract():
         try:
             assert lib.ps_plan_set_variant(r, 0, 4) == S.PS_ERR_UNSUPPORTED  # 32 FP64 rows of 1024: too much LDS
             assert lib.ps_plan_set_variant(r, 0, 2) == S.PS_OK
+            # half-LDS z exchange: FP64 cubes with P >= 512
+            assert lib.ps_plan_set_variant(r, 2, 5) == S.PS_OK and lib.ps_plan_set_variant(r, 2, 6) == S.PS_ERR_INVALID
         finally:
             S.ps_plan_destroy(r)
         r = S.ps_plan_create(512, 1.0 / 512, S.PS_F32)
         try:
             assert lib.ps_plan_set_variant(r, 0, 4) == S.PS_OK and lib.ps_plan_set_variant(r, 4, 5) == S.PS_OK
+            assert lib.ps_plan_set_variant(r, 2, 5) == S.PS_ERR_UNSUPPORTED  # half-LDS z exchange: FP64 only
         finally:
             S.ps_plan_destroy(r)
         assert lib.ps_plan_set_variant(p, 5, 6) == S.PS_ERR_UNSUPPORTED  # product terms: split plans only
-        assert lib.ps_plan_set_variant(p, 2, 5) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 2, 6) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 2, 5) == S.PS_ERR_UNSUPPORTED  # P = 64
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED  # no radix-32 family at P = 64
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
@@ -252,8 +256,8 @@ def test_tuning_cache_is_read(tmp_path):
     finally:
         S.ps_plan_destroy(p)
     # measured defaults: variants and z tile
-    for n, prec, want, zt in [(512, S.PS_F32, [0, 1, 3, 3, 2], 0), (512, S.PS_F64, [2, 1, 2, 2, 2], 1),
-                              (256, S.PS_F64, [2, 1, 4, 0, 2], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 4, 2], 1),
+    for n, prec, want, zt in [(512, S.PS_F32, [0, 1, 3, 3, 2], 0), (512, S.PS_F64, [2, 1, 5, 2, 2], 0),
+                              (256, S.PS_F64, [2, 1, 5, 0, 2], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 4, 2], 1),
                               (128, S.PS_F32, [0, 0, 1, 0, 0], 0), (512, S.PS_F32_SPLIT, [0, 0, 1, 4, 0], 1),
                               (384, S.PS_F32, [0, 1, 2, 0, 2], 1), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
