@@ -226,8 +226,8 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * radix-16-based), 4 = persistent on the radix-16-based plan with fewer
  * pencils per wavefront, 5 = wavefront-owned pencils on the two-stage plan
  * whose stage exchanges pass through half the LDS in two rounds (twice as
- * many pencils resident per compute unit): PS_F64 cubes with n >= 256 only
- * (PS_ERR_UNSUPPORTED otherwise).  Boxes (ps_plan_create_box with unequal lengths)
+ * many pencils resident per compute unit): PS_F64 and PS_F32 cubes with
+ * n >= 256 only (PS_ERR_UNSUPPORTED otherwise).  Boxes (ps_plan_create_box with unequal lengths)
  * run the one-tile-per-workgroup variants only: y passes 0 and 1, z pass 0,
  * 1 and 2 (PS_ERR_UNSUPPORTED otherwise); the two-stage plan follows
  * the length of the axis the pass transforms.  Every variant computes the

@@ -363,10 +363,10 @@ __global__ __launch_bounds__(NT) void k_z_conv(const cx<T>* in, cx<T>* out, cons
 // Fused z pass whose exchanges go through half the LDS in two rounds
 // (wave-owned pencils, one tile per workgroup): a pencil holds a row of P/2
 // instead of P, so twice as many pencils stay resident on a compute unit.
-// Meant for 16-byte elements, where a 1024-point pencil's full row (16 KB)
-// limits a compute unit to about eight; on the two-stage plans (two or more
-// pencils per wavefront, up to 251 registers a lane) the rows of two
-// workgroups of eight pencils fit where one did.  The last inverse stage reads
+// On the two-stage plans (two or more pencils per wavefront) the rows of two
+// workgroups fit where one did: FP64 holds 16 instead of 8 1024-point
+// pencils per compute unit, FP32 32 instead of 16 (four wavefronts per SIMD
+// instead of two).  The last inverse stage reads
 // pencil-fastest, so the stores of the cropped output stay coalesced.
 template <typename T, int P, int FAM, int B, int NT>
 __global__ __launch_bounds__(NT) void k_z_conv_half(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,

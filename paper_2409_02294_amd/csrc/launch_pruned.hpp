@@ -275,7 +275,7 @@ template <typename T, int P, int MT, int B> static void cube_z(int zmode, const 
             return;
         }
     }
-    if constexpr (std::is_same<T, double>::value && P >= 512 && F1) {
+    if constexpr (P >= 512 && F1) {
         if (zmode == 5) {  // half-LDS exchange on the two-stage plan
             L1::template z_conv_half<B>(b);
             return;

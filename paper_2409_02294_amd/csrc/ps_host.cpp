@@ -422,9 +422,9 @@ bool variant_ok(ps_plan p, int pass, int variant)
     // boxes run the one-tile-per-workgroup kernels only
     if (p->box && (pass == 1 || pass == 3) && (variant & 6)) return false;
     if (p->box && pass == 2 && variant >= 3) return false;
-    // half-LDS z exchange: double-precision cubes with P >= 512 (where the
-    // 16-byte rows otherwise bound the pencils resident per compute unit)
-    if (pass == 2 && variant >= 5 && (p->prec != PS_F64 || axis_pad(p, 2) < 512)) return false;
+    // half-LDS z exchange: FP64 and FP32 cubes with P >= 512 (where the LDS
+    // rows otherwise bound the pencils resident per compute unit)
+    if (pass == 2 && variant >= 5 && ((p->prec != PS_F64 && p->prec != PS_F32) || axis_pad(p, 2) < 512)) return false;
     return true;
 }
 
@@ -467,12 +467,12 @@ const ZDefault Z_DEFAULTS[] = {
     { 480, {3, 2, 1}, {1, 1, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {-1, 5, -1}},
     { 512, {5, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
     { 576, {2, 2, 1}, {0, 0, 0}, {2, 1, -1}, {2, 1, 2}, {1, 1, 4}, {1, 5, -1}},
-    { 640, {5, 2, 1}, {1, 1, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
+    { 640, {5, 5, 1}, {1, 0, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
     { 720, {5, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 2, 2}, {1, 4, 4}, {4, 5, 4}},
-    { 768, {0, 2, 1}, {1, 1, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 1, -1}, {-1, -1, 4}},
-    { 800, {5, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 3, 2}, {1, 1, -1}, {4, 5, 4}},
-    { 864, {5, 2, 1}, {1, 0, 0}, {3, 1, -1}, {3, 3, 2}, {1, 1, -1}, {5, 5, 4}},
-    { 960, {5, 2, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {-1, 4, 4}},
+    { 768, {0, 5, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 1, -1}, {-1, -1, 4}},
+    { 800, {5, 5, 1}, {1, 1, 0}, {2, 1, -1}, {2, 3, 2}, {1, 1, -1}, {4, 5, 4}},
+    { 864, {5, 5, 1}, {1, 0, 0}, {3, 1, -1}, {3, 3, 2}, {1, 1, -1}, {5, 5, 4}},
+    { 960, {5, 5, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {-1, 4, 4}},
     {1024, {5, 3, 1}, {0, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, 4}},
 };
 

@@ -178,12 +178,17 @@ def test_variant_selection_contract():
         r = S.ps_plan_create(512, 1.0 / 512, S.PS_F32)
         try:
             assert lib.ps_plan_set_variant(r, 0, 4) == S.PS_OK and lib.ps_plan_set_variant(r, 4, 5) == S.PS_OK
-            assert lib.ps_plan_set_variant(r, 2, 5) == S.PS_ERR_UNSUPPORTED  # half-LDS z exchange: FP64 only
+            assert lib.ps_plan_set_variant(r, 2, 5) == S.PS_OK
         finally:
             S.ps_plan_destroy(r)
         assert lib.ps_plan_set_variant(p, 5, 6) == S.PS_ERR_UNSUPPORTED  # product terms: split plans only
         assert lib.ps_plan_set_variant(p, 2, 6) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 2, 5) == S.PS_ERR_UNSUPPORTED  # P = 64
+        sp = S.ps_plan_create(256, 1.0 / 256, S.PS_F32_SPLIT)
+        try:
+            assert lib.ps_plan_set_variant(sp, 2, 5) == S.PS_ERR_UNSUPPORTED  # split plans: radix-16 stages only
+        finally:
+            S.ps_plan_destroy(sp)
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED  # no radix-32 family at P = 64
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED
@@ -259,7 +264,7 @@ def test_tuning_cache_is_read(tmp_path):
     for n, prec, want, zt in [(512, S.PS_F32, [0, 1, 3, 3, 2], 0), (512, S.PS_F64, [2, 1, 5, 2, 2], 0),
                               (256, S.PS_F64, [2, 1, 5, 0, 2], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 4, 2], 1),
                               (128, S.PS_F32, [0, 0, 1, 0, 0], 0), (512, S.PS_F32_SPLIT, [0, 0, 1, 4, 0], 1),
-                              (384, S.PS_F32, [0, 1, 2, 0, 2], 1), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
+                              (384, S.PS_F32, [0, 1, 5, 0, 2], 0), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
         try:
             info = S.ps_plan_query(p)
