@@ -215,7 +215,11 @@ ps_status ps_solve_batched(const ps_plan *plans, int count, const void *const *d
  * take 2 and 3, the same plans run by persistent workgroups that load the
  * next tile while transforming the current one, and 4 and 5, the plans of 0
  * and 1 with half as many pencils per workgroup (8 in float, 4 in double:
- * 64-byte output rows, half the LDS); passes 0 and 4 (the x
+ * 64-byte output rows, half the LDS), and 6 and 7, the plans of 0 and 1
+ * with every stage exchange through half the LDS in two rounds (twice the
+ * workgroups resident per compute unit, the full tile's 128-byte rows;
+ * PS_F64 and PS_F32 cubes with n >= 256 only, PS_ERR_UNSUPPORTED
+ * otherwise); passes 0 and 4 (the x
  * passes) also take 2 and 3 (8 rows of a z-plane per workgroup instead of
  * 16) and 4 and 5 (32 rows, where the LDS holds them; PS_ERR_UNSUPPORTED
  * otherwise), the family again in the low bit.  Pass 2 (the fused z pass): 0 =

@@ -469,6 +469,19 @@ template <typename T, class RP, int B, int NT, bool WSYNC = false, int MT = 0, i
         }
     }
 
+    // Full transform as run(), every stage exchange through half the LDS
+    // (LPH: its row pitch); stage 0 and the middle stages use MAP_IN.
+    template <int DIR, int MAP_IN, int MAP_OUT, int LIN, int LOUT, int LPH, class LD, class ST>
+    __device__ __forceinline__ static void run_half(V* lds, const TW& tw, LD& ld, ST& st, const SA& sa = SA{})
+    {
+        static_assert(S > 1, "two or more stages");
+        Regs<0> g;
+        load_first<MAP_IN, LIN>(g, ld);
+        Regs<S - 1> h;
+        stages_half<0, DIR, MAP_IN, MAP_OUT, MAP_IN, LPH>(g, h, lds, tw, sa);
+        store_last<MAP_OUT, LOUT>(h, st);
+    }
+
     // Stage-0 inputs from ld(p, idx); idx >= LIN reads as zero.
     template <int MAP, int LIN, class LD> __device__ __forceinline__ static void load_first(Regs<0>& g, LD& ld)
     {

@@ -120,14 +120,22 @@ template <typename T, int P, int FAM, int NT, int MAP_MID, int MT, bool BOX = fa
     }
 };
 
+// Wavefronts per SIMD for two resident workgroups of NT threads: the register
+// budget the half-LDS forms are compiled to, so that the halved LDS rows do
+// let a second workgroup onto the compute unit.
+constexpr int half_waves_per_simd(int NT) { return NT / 128 > 1 ? NT / 128 : 1; }
+
 // ---------------------------------------------------------------------------
 // y_fwd: ZT z-pencils of one kx; tile (z-tile bx, kx by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false> struct TileYFwd {
+// HALF: stage exchanges through half the LDS in two rounds (twice the
+// workgroups resident per compute unit, the same 128-byte output rows).
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false, bool HALF = false>
+struct TileYFwd {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Fwd, ZT, NT, false, MT>;
     static constexpr int N = P / 2;  // y length
-    static constexpr int LDS = E::LDS_ELEMS;
+    static constexpr int LDS = HALF ? ZT * E::half_pitch() : E::LDS_ELEMS;
     __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t1, V* __restrict__ t2,
                                                const V* __restrict__ tw, V* lds, const typename E::SA& sa,
                                                int nz_box = 0)
@@ -143,7 +151,8 @@ template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool 
         auto st = [&](int p, int idx, V v) {
             if (z0 + p < Nz) out[(unsigned)(idx * Nz + p)] = v;
         };
-        E::template run<-1, MAP_EF, MAP_MID, MAP_PF, N, P>(lds, tw, ld, st, sa);
+        if constexpr (HALF) E::template run_half<-1, MAP_EF, MAP_PF, N, P, E::half_pitch()>(lds, tw, ld, st, sa);
+        else E::template run<-1, MAP_EF, MAP_MID, MAP_PF, N, P>(lds, tw, ld, st, sa);
     }
 };
 
@@ -197,11 +206,12 @@ template <typename T, int P, int FAM, int B, int NT, bool WAVE, int MT, bool BOX
 // ---------------------------------------------------------------------------
 // y_inv: ZT consecutive kx pencils of one z; tile (kx-tile bx, z by).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false> struct TileYInv {
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false, bool HALF = false>
+struct TileYInv {
     using V = cx<T>;
     using E = Engine<T, typename PlanFor<P, FAM>::Inv, ZT, NT, false, MT>;
     static constexpr int N = P / 2;  // y length
-    static constexpr int LDS = E::LDS_ELEMS;
+    static constexpr int LDS = HALF ? ZT * E::half_pitch() : E::LDS_ELEMS;
     __device__ __forceinline__ static void run(int bx, int by, const V* __restrict__ t3, V* __restrict__ t4,
                                                const V* __restrict__ tw, V* lds, const typename E::SA& sa,
                                                int nx_box = 0, int nz_box = 0)
@@ -217,7 +227,8 @@ template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool 
         auto st = [&](int p, int idx, V v) {
             if (kx0 + p < Hx) out[(unsigned)(idx * HP + p)] = v;
         };
-        E::template run<+1, MAP_EF, MAP_MID, MAP_PF, P, N>(lds, tw, ld, st, sa);
+        if constexpr (HALF) E::template run_half<+1, MAP_EF, MAP_PF, P, N, E::half_pitch()>(lds, tw, ld, st, sa);
+        else E::template run<+1, MAP_EF, MAP_MID, MAP_PF, P, N>(lds, tw, ld, st, sa);
     }
 };
 
@@ -313,11 +324,11 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const T* in, cx<T>* out, const Sol
             lds, sa, ext<BOX>(s.ny, 0), ext<BOX>(s.nz, 0));
 }
 
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false>
-__global__ __launch_bounds__(NT) void k_y_fwd(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false, bool HALF = false>
+__global__ __launch_bounds__(NT, HALF ? half_waves_per_simd(NT) : 1) void k_y_fwd(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileYFwd<T, P, FAM, ZT, NT, MAP_MID, MT, BOX>;
+    using TL = TileYFwd<T, P, FAM, ZT, NT, MAP_MID, MT, BOX, HALF>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;
@@ -598,11 +609,11 @@ __global__ __launch_bounds__(NT) void k_z_conv_pf(const cx<T>* in, cx<T>* out, c
     }
 }
 
-template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false>
-__global__ __launch_bounds__(NT) void k_y_inv(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
+template <typename T, int P, int FAM, int ZT, int NT, int MAP_MID, int MT, bool BOX = false, bool HALF = false>
+__global__ __launch_bounds__(NT, HALF ? half_waves_per_simd(NT) : 1) void k_y_inv(const cx<T>* in, cx<T>* out, const SolveRec* __restrict__ list,
                                               const unsigned short* __restrict__ stab)
 {
-    using TL = TileYInv<T, P, FAM, ZT, NT, MAP_MID, MT, BOX>;
+    using TL = TileYInv<T, P, FAM, ZT, NT, MAP_MID, MT, BOX, HALF>;
     using V = cx<T>;
     __shared__ V lds[TL::LDS];
     typename TL::E::SA sa;

@@ -74,10 +74,11 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
                            b.stab);
     }
     // y passes: Z pencils per workgroup (the full tile ZT or half of it)
-    template <int Z = ZT> static void y_fwd(const PrunedBufs& b)
+    // (HALF: stage exchanges through half the LDS in two rounds)
+    template <int Z = ZT, bool HALF = false> static void y_fwd(const PrunedBufs& b)
     {
         constexpr int NTZY = threads_for(Z, P, E);
-        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, Z, NTZY, MAP_EF, MT>), dim3((N + Z - 1) / Z, H, b.count), dim3(NTZY),
+        hipLaunchKernelGGL((k_y_fwd<T, P, FAM, Z, NTZY, MAP_EF, MT, false, HALF>), dim3((N + Z - 1) / Z, H, b.count), dim3(NTZY),
                            0, b.stream, static_cast<const V*>(b.in[1]), static_cast<V*>(b.out[1]), b.list, b.stab);
     }
     // z pass: B pencils per workgroup (the full tile ZB or half of it)
@@ -123,10 +124,10 @@ template <typename T, int P, int FAM, int MT> struct PassLaunch {
                            0, b.stream, static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab,
                            b.count);
     }
-    template <int Z = ZT> static void y_inv(const PrunedBufs& b)
+    template <int Z = ZT, bool HALF = false> static void y_inv(const PrunedBufs& b)
     {
         constexpr int NTZY = threads_for(Z, P, E);
-        hipLaunchKernelGGL((k_y_inv<T, P, FAM, Z, NTZY, MAP_EF, MT>), dim3((H + Z - 1) / Z, N, b.count), dim3(NTZY),
+        hipLaunchKernelGGL((k_y_inv<T, P, FAM, Z, NTZY, MAP_EF, MT, false, HALF>), dim3((H + Z - 1) / Z, N, b.count), dim3(NTZY),
                            0, b.stream, static_cast<const V*>(b.in[3]), static_cast<V*>(b.out[3]), b.list, b.stab);
     }
     template <int ROWS = 16> static void x_c2r(const PrunedBufs& b)
@@ -299,9 +300,17 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
         case 0:
             if (!x_pass<T, P, MT>(false, v.x_fam, b)) return hipErrorInvalidValue;
             break;
-        case 1:  // variant bit 0: radix-32 family, bit 1: persistent
-            // variant bit 0: radix-32 family, bit 1: persistent, 4 and 5: half tile
-            if (v.y_fam >= 4) {
+        case 1:
+            // variant bit 0: two-stage family, bit 1: persistent, 4 and 5: half
+            // tile, 6 and 7: stage exchanges through half the LDS
+            if (v.y_fam >= 6) {
+                if constexpr (P >= 512 && MT == 0) {
+                    if ((v.y_fam & 1) && F1) L1::template y_fwd<PrunedShape<T>::ZT, true>(b);
+                    else L0::template y_fwd<PrunedShape<T>::ZT, true>(b);
+                } else {
+                    return hipErrorInvalidValue;
+                }
+            } else if (v.y_fam >= 4) {
                 if ((v.y_fam & 1) && F1) L1::template y_fwd<PrunedShape<T>::ZT / 2>(b);
                 else L0::template y_fwd<PrunedShape<T>::ZT / 2>(b);
             } else if ((v.y_fam & 1) && F1) (v.y_fam & 2) ? L1::y_fwd_pf(b) : L1::y_fwd(b);
@@ -312,7 +321,14 @@ template <typename T, int P, int MT> static hipError_t pruned_passes(int lo, int
             else cube_z<T, P, MT, PrunedShape<T>::ZB>(v.zmode, b);
             break;
         case 3:
-            if (v.yi_fam >= 4) {
+            if (v.yi_fam >= 6) {
+                if constexpr (P >= 512 && MT == 0) {
+                    if ((v.yi_fam & 1) && F1) L1::template y_inv<PrunedShape<T>::ZT, true>(b);
+                    else L0::template y_inv<PrunedShape<T>::ZT, true>(b);
+                } else {
+                    return hipErrorInvalidValue;
+                }
+            } else if (v.yi_fam >= 4) {
                 if ((v.yi_fam & 1) && F1) L1::template y_inv<PrunedShape<T>::ZT / 2>(b);
                 else L0::template y_inv<PrunedShape<T>::ZT / 2>(b);
             } else if ((v.yi_fam & 1) && F1) (v.yi_fam & 2) ? L1::y_inv_pf(b) : L1::y_inv(b);

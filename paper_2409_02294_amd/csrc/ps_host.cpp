@@ -353,7 +353,7 @@ const char* prec_name(ps_precision p)
 
 // pass 6 (z tile): 2 values; x passes: family bit + 2 x rows selector (16, 8, 32 rows);
 // y passes: family bit + 2 x persistent bit, or 4 + family bit (half tile)
-int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : 6; }
+int num_variants(int pass) { return pass == 2 ? ps::NUM_ZMODES : (pass == 1 || pass == 3) ? 8 : 6; }
 
 // Whether variant v of a pass runs the radix-32-based plan family.
 bool variant_needs_family1(int pass, int v)
@@ -425,6 +425,9 @@ bool variant_ok(ps_plan p, int pass, int variant)
     // half-LDS z exchange: FP64 and FP32 cubes with P >= 512 (where the LDS
     // rows otherwise bound the pencils resident per compute unit)
     if (pass == 2 && variant >= 5 && ((p->prec != PS_F64 && p->prec != PS_F32) || axis_pad(p, 2) < 512)) return false;
+    // half-LDS y exchanges (6, 7): the same plans
+    if ((pass == 1 || pass == 3) && variant >= 6 && ((p->prec != PS_F64 && p->prec != PS_F32) || axis_pad(p, 1) < 512))
+        return false;
     return true;
 }
 
@@ -465,15 +468,15 @@ const ZDefault Z_DEFAULTS[] = {
     { 400, {3, 3, 1}, {1, 0, 0}, {2, 3, 2}, {3, 3, -1}, {-1, 5, -1}, {1, 1, -1}},
     { 432, {3, 3, 1}, {0, 0, 0}, {1, 3, -1}, {3, 3, -1}, {1, 5, -1}, {1, 1, -1}},
     { 480, {3, 2, 1}, {1, 1, 1}, {-1, -1, -1}, {2, 2, 2}, {-1, 2, -1}, {-1, 5, -1}},
-    { 512, {5, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, -1, -1}, {-1, -1, 4}},
-    { 576, {2, 2, 1}, {0, 0, 0}, {2, 1, -1}, {2, 1, 2}, {1, 1, 4}, {1, 5, -1}},
-    { 640, {5, 5, 1}, {1, 0, 1}, {2, 1, -1}, {2, 2, 2}, {3, 1, 2}, {4, 5, 4}},
-    { 720, {5, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 2, 2}, {1, 4, 4}, {4, 5, 4}},
-    { 768, {0, 5, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 1, -1}, {-1, -1, 4}},
-    { 800, {5, 5, 1}, {1, 1, 0}, {2, 1, -1}, {2, 3, 2}, {1, 1, -1}, {4, 5, 4}},
-    { 864, {5, 5, 1}, {1, 0, 0}, {3, 1, -1}, {3, 3, 2}, {1, 1, -1}, {5, 5, 4}},
-    { 960, {5, 5, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {-1, 4, 4}},
-    {1024, {5, 3, 1}, {0, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, -1, -1}, {-1, -1, 4}},
+    { 512, {5, 3, 4}, {0, 0, 1}, {2, -1, -1}, {2, -1, -1}, {-1, 6, -1}, {-1, -1, 4}},
+    { 576, {2, 2, 1}, {0, 0, 0}, {2, 1, -1}, {2, 1, 2}, {1, 7, 4}, {1, 7, -1}},
+    { 640, {5, 5, 1}, {1, 0, 1}, {2, 1, -1}, {2, 2, 2}, {7, 7, 2}, {7, 7, 4}},
+    { 720, {5, 2, 1}, {1, 1, 0}, {2, 1, -1}, {2, 2, 2}, {7, 7, 4}, {7, 7, 4}},
+    { 768, {0, 5, 1}, {1, 0, 1}, {2, -1, -1}, {2, 2, 2}, {-1, 7, -1}, {7, 7, 4}},
+    { 800, {5, 5, 1}, {1, 1, 0}, {2, 1, -1}, {2, 3, 2}, {1, 7, -1}, {7, 7, 4}},
+    { 864, {5, 5, 1}, {1, 0, 0}, {3, 1, -1}, {3, 3, 2}, {1, 7, -1}, {7, 7, 4}},
+    { 960, {5, 5, 1}, {1, 1, 0}, {2, -1, -1}, {2, 3, -1}, {1, 1, -1}, {6, 7, 4}},
+    {1024, {5, 3, 1}, {0, 0, 1}, {2, -1, -1}, {2, 2, -1}, {-1, 7, -1}, {-1, -1, 4}},
 };
 
 // The measured defaults of length P, and the precision's column in them.

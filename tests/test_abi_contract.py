@@ -164,15 +164,17 @@ def test_variant_selection_contract():
         # y passes: half tile (4: radix-16 family, 5: radix-32 family)
         assert lib.ps_plan_set_variant(p, 1, 4) == S.PS_OK and lib.ps_plan_set_variant(p, 3, 4) == S.PS_OK
         assert lib.ps_plan_set_variant(p, 1, 5) == S.PS_ERR_UNSUPPORTED
-        assert lib.ps_plan_set_variant(p, 3, 6) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 3, 8) == S.PS_ERR_INVALID
+        assert lib.ps_plan_set_variant(p, 3, 6) == S.PS_ERR_UNSUPPORTED  # half-LDS y exchange: P >= 512
         assert lib.ps_plan_set_variant(q, 3, 5) == S.PS_OK
         assert lib.ps_plan_set_variant(q, 4, 5) == S.PS_OK               # 32 rows, radix-32 family, FP64 P = 512
         r = S.ps_plan_create(512, 1.0 / 512, S.PS_F64)
         try:
             assert lib.ps_plan_set_variant(r, 0, 4) == S.PS_ERR_UNSUPPORTED  # 32 FP64 rows of 1024: too much LDS
             assert lib.ps_plan_set_variant(r, 0, 2) == S.PS_OK
-            # half-LDS z exchange: FP64 cubes with P >= 512
+            # half-LDS z and y exchanges: FP64 and FP32 cubes with P >= 512
             assert lib.ps_plan_set_variant(r, 2, 5) == S.PS_OK and lib.ps_plan_set_variant(r, 2, 6) == S.PS_ERR_INVALID
+            assert lib.ps_plan_set_variant(r, 1, 7) == S.PS_OK and lib.ps_plan_set_variant(r, 3, 6) == S.PS_OK
         finally:
             S.ps_plan_destroy(r)
         r = S.ps_plan_create(512, 1.0 / 512, S.PS_F32)
@@ -187,6 +189,7 @@ def test_variant_selection_contract():
         sp = S.ps_plan_create(256, 1.0 / 256, S.PS_F32_SPLIT)
         try:
             assert lib.ps_plan_set_variant(sp, 2, 5) == S.PS_ERR_UNSUPPORTED  # split plans: radix-16 stages only
+            assert lib.ps_plan_set_variant(sp, 1, 6) == S.PS_ERR_UNSUPPORTED
         finally:
             S.ps_plan_destroy(sp)
         assert lib.ps_plan_set_variant(p, 0, -1) == S.PS_ERR_INVALID
@@ -239,11 +242,12 @@ def test_tuning_cache_is_read(tmp_path):
         assert info["variant"] == [1, 1, 2, 1, 1] and info["z_tile"] == 1
     finally:
         S.ps_plan_destroy(p)
-    # a missing file keeps the defaults (radix-32 family for the forward y pass
-    # and the FP32 z pass at P = 512, radix-16 family elsewhere)
+    # a missing file keeps the defaults (the forward y pass exchanging through
+    # half the LDS and the persistent z pass at P = 512, radix-16 family
+    # elsewhere)
     p = S.ps_plan_create(256, 1.0 / 256, S.PS_F32, str(tmp_path / "absent.txt"))
     try:
-        assert S.ps_plan_query(p)["variant"] == [0, 1, 3, 0, 0]
+        assert S.ps_plan_query(p)["variant"] == [0, 6, 3, 0, 0]
     finally:
         S.ps_plan_destroy(p)
     # a split plan keeps its product-term count under a cached line; a line
@@ -261,10 +265,10 @@ def test_tuning_cache_is_read(tmp_path):
     finally:
         S.ps_plan_destroy(p)
     # measured defaults: variants and z tile
-    for n, prec, want, zt in [(512, S.PS_F32, [0, 1, 3, 3, 2], 0), (512, S.PS_F64, [2, 1, 5, 2, 2], 0),
+    for n, prec, want, zt in [(512, S.PS_F32, [0, 7, 3, 3, 2], 0), (512, S.PS_F64, [2, 1, 5, 2, 2], 0),
                               (256, S.PS_F64, [2, 1, 5, 0, 2], 0), (384, S.PS_F32_SPLIT, [0, 0, 1, 4, 2], 1),
                               (128, S.PS_F32, [0, 0, 1, 0, 0], 0), (512, S.PS_F32_SPLIT, [0, 0, 1, 4, 0], 1),
-                              (384, S.PS_F32, [0, 1, 5, 0, 2], 0), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
+                              (384, S.PS_F32, [0, 7, 5, 7, 2], 0), (16, S.PS_F64, [0, 0, 1, 0, 0], 0)]:
         p = S.ps_plan_create(n, 1.0 / n, prec, None)
         try:
             info = S.ps_plan_query(p)

@@ -279,6 +279,30 @@ def test_blobs512_sampled_direct_sum(prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [256, 360, 400, 512])
+def test_half_lds_y_exchange(prec, n):
+    # the y passes exchanging through half the LDS in two rounds (both plan
+    # families) against the one-round passes
+    rho_np = inputs.make_density(n, 12, 7100 + n, sigma=(0.02, 0.06), noise=1e-3)
+    s = S.Solver(n, 1.0 / n, prec)
+    rho = torch.from_numpy(rho_np).to("cuda", _dtype(prec))
+    S.ps_plan_set_variant(s.plan, 1, 0)
+    S.ps_plan_set_variant(s.plan, 3, 0)
+    base = s(rho)
+    for yf, yi in ((6, 6), (7, 7), (6, 7), (7, 6)):
+        S.ps_plan_set_variant(s.plan, 1, yf)
+        S.ps_plan_set_variant(s.plan, 3, yi)
+        got = s(rho)
+        again = s(rho)
+        l2 = float((got - base).norm() / base.norm())
+        print(f"n={n} {prec} y variants {yf}/{yi}: relL2 vs one-round exchange {l2:.2e}", flush=True)
+        assert torch.equal(got, again)
+        assert l2 <= (1e-13 if prec == "f64" else 5e-7)
+    del s, rho, base
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n", [256, 320, 400, 432, 480, 512])
 def test_half_lds_z_exchange(prec, n):
     # the z pass exchanging through half the LDS in two rounds (both tile
@@ -363,12 +387,13 @@ def test_variants_agree_n256(prec):
         S.ps_plan_set_variant(s.plan, k, 0)
     base = s(rho).double().cpu().numpy()
     tol = 1e-13 if prec == "f64" else 5e-7
-    for k, nv in zip(range(5), (6, 6, 6, 6, 6)):
+    for k, nv in zip(range(5), (6, 8, 6, 8, 6)):
         for v in range(1, nv):
             try:
                 S.ps_plan_set_variant(s.plan, k, v)
             except S.PSError:
-                assert k == 2 and v == 5 and prec == "f32_split"  # half-LDS z exchange: not split
+                # half-LDS z and y exchanges: not split
+                assert ((k == 2 and v == 5) or (k in (1, 3) and v >= 6)) and prec == "f32_split"
                 continue
             got = s(rho).double().cpu().numpy()
             l2 = oracle.rel_l2(got, base)
