@@ -360,6 +360,7 @@ def test_box_plan_contract():
         assert info["variant"] == [0, 1, 1, 0, 0]  # radix-32 family for y (P = 512), wave-owned z
         assert S.ps_host_stage_bytes(p) == 4 * ((nx * ny * nz * 4 + 255) // 256 * 256)
         assert lib.ps_plan_set_variant(p, 1, 2) == S.PS_ERR_UNSUPPORTED   # persistent y pass: cubes only
+        assert lib.ps_plan_set_variant(p, 1, 7) == S.PS_ERR_UNSUPPORTED   # half-LDS y exchange: cubes only
         assert lib.ps_plan_set_variant(p, 2, 3) == S.PS_ERR_UNSUPPORTED   # persistent z pass: cubes only
         assert lib.ps_plan_set_variant(p, 2, 2) == S.PS_ERR_UNSUPPORTED   # P = 48 along z: no radix-32 family
         assert lib.ps_plan_set_variant(p, 0, 1) == S.PS_ERR_UNSUPPORTED   # P = 80 along x: no radix-32 family

@@ -539,6 +539,29 @@ def test_autotune_writes_cache(tmp_path):
     assert oracle.rel_l2(got, ref) <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_autotune_n256_includes_half_lds_forms(prec, tmp_path):
+    # at P = 512 the autotuner also times the half-LDS y and z forms; its
+    # choice, read back from the cache, solves to rounding of the defaults
+    n = 256
+    s = S.Solver(n, 1.0 / n, prec)
+    rho = torch.from_numpy(inputs.make_density(n, 8, 4242, sigma=(0.02, 0.06), noise=1e-3)).to("cuda", _dtype(prec))
+    base = s(rho)
+    path = str(tmp_path / "tune.txt")
+    S.ps_autotune(s.plan, torch.cuda.current_stream().cuda_stream, path)
+    fields = open(path).read().split()
+    assert fields[:2] == ["512", prec] and len(fields) == 8
+    s2 = S.Solver(n, 1.0 / n, prec, tune_cache=path)
+    assert (s2.info()["variant"], s2.info()["z_tile"]) == (s.info()["variant"], s.info()["z_tile"])
+    got = s2(rho)
+    l2 = float((got - base).norm() / base.norm())
+    print(f"n=256 {prec} autotuned {s2.info()['variant']} z tile {s2.info()['z_tile']}: relL2 vs defaults {l2:.2e}",
+          flush=True)
+    assert l2 <= (1e-13 if prec == "f64" else 5e-7)
+    del s, s2, rho, base, got
+    torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------------------
 # Split-bf16 matrix-core DFT-16: the six-term form meets the single-precision
 # bound; the three-term form is reported (it is the labelled, less accurate
